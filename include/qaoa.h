@@ -1,0 +1,168 @@
+/*
+ * qaoa.h -- C ABI of the MI355X (gfx950) QAOA statevector library.
+ *
+ * The library simulates depth-p QAOA for a diagonal cost C on n qubits
+ * (Eq. (1)):  psi(gamma, beta) = U_M(beta_p) U_C(gamma_p) ... U_M(beta_1) U_C(gamma_1) |+>^n
+ * with U_C(g) = exp(-i g C) and U_M(b) = prod_j exp(-i b X_j).
+ *
+ * Conventions shared by every call
+ *   - Qubit / binary variable i is bit i of the basis index z (Eq. (2) uses 2^i).
+ *   - Mixer sign: exp(-i b X) per qubit (the Farhi form).  The paper writes
+ *     H_M = -sum X, i.e. exp(+i b X); its angles map to ours by b -> -b.
+ *   - The objective is E = <psi|C|psi> with C the cut weight (MaxCut) or the
+ *     0-1 polynomial value (QUBO); gradients are of E itself.
+ *   - Host arrays passed in are copied during the call; the caller keeps them.
+ *   - Every call validates its arguments before touching the GPU; on any error
+ *     the outputs and the handle are left unchanged, except QAOA_ERR_DEVICE,
+ *     which marks the handle unusable (qaoa_destroy stays valid).  Nothing
+ *     throws or aborts across this boundary.
+ *   - Work is ordered on the handle's HIP stream.  Calls that return values in
+ *     host memory synchronise that stream before returning; device outputs are
+ *     stream-ordered.  One thread may use a handle at a time; distinct handles
+ *     are independent.
+ *   - Complex amplitudes are interleaved (re, im): complex128 = 2 x fp64,
+ *     complex64 = 2 x fp32, matching numpy/torch complex dtypes.
+ */
+#ifndef QAOA_MI355X_QAOA_H
+#define QAOA_MI355X_QAOA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qaoa_handle_s *qaoa_handle;
+
+typedef enum {
+    QAOA_OK = 0,
+    QAOA_ERR_INVALID_ARGUMENT = 1, /* bad size, index, NULL pointer, non-finite value */
+    QAOA_ERR_OUT_OF_MEMORY = 2,    /* device buffers do not fit (checked before allocating) */
+    QAOA_ERR_DEVICE = 3,           /* a HIP call failed; the handle is now unusable */
+    QAOA_ERR_NO_STATE = 4,         /* the call needs a current state (qaoa_statevector first) */
+    QAOA_ERR_UNSUPPORTED = 5
+} qaoa_status;
+
+typedef enum {
+    QAOA_C128 = 0, /* complex128 state, fp64 cost diagonal */
+    QAOA_C64 = 1   /* complex64 state, fp32 cost diagonal; phases reduced in fp64, sums in fp64 */
+} qaoa_precision;
+
+/* Largest supported qubit count (further bounded by free device memory). */
+#define QAOA_MAX_QUBITS 40
+
+/*
+ * Create a handle for weighted MaxCut (Sec. V: MaxCut benchmark; Sec. IV-A: cost
+ * function representation).  C(z) = sum of w[k] over edges k = (i, j) with
+ * bit i of z != bit j of z, added in edge order (so integer weights give exact
+ * values).
+ *   n       1 <= n <= QAOA_MAX_QUBITS
+ *   m       number of edges, m >= 0
+ *   edges   host int32 [m][2]; 0 <= i, j < n, i != j; repeated edges add
+ *   w       host fp64 [m], finite; NULL means unit weights
+ *   precision  a qaoa_precision value
+ *   stream  hipStream_t to order all work on; NULL creates a private stream
+ *   out     receives the handle
+ * The handle allocates the state and cost diagonal on the current HIP device
+ * (Sec. IV-B: state and cost arrays at initialisation, other buffers lazily when
+ * first needed).  The cost diagonal is built here.
+ * Errors: INVALID_ARGUMENT, OUT_OF_MEMORY (2^n buffers exceed free memory), DEVICE.
+ */
+qaoa_status qaoa_create_maxcut(int32_t n, int64_t m, const int32_t *edges, const double *w,
+                               int32_t precision, void *stream, qaoa_handle *out);
+
+/*
+ * Create a handle for a 0-1 QUBO, the degree-2 case of Eq. (2):
+ * C(z) = offset + sum_k J[k] x_i x_j + sum_i h[i] x_i,  x_i = bit i of z,
+ * accumulated as offset, then pair terms in the given order, then linear
+ * terms in variable order.
+ *   pairs   host int32 [m][2], 0 <= i, j < n, i != j
+ *   J       host fp64 [m] (may be NULL when m == 0)
+ *   h       host fp64 [n] or NULL (no linear terms)
+ *   offset  finite constant
+ * Other arguments and errors as qaoa_create_maxcut.
+ */
+qaoa_status qaoa_create_qubo(int32_t n, int64_t m, const int32_t *pairs, const double *J,
+                             const double *h, double offset, int32_t precision, void *stream,
+                             qaoa_handle *out);
+
+/* Release every device buffer and the private stream.  NULL is a no-op. */
+qaoa_status qaoa_destroy(qaoa_handle h);
+
+/* Report n and the precision of a handle (either output pointer may be NULL). */
+qaoa_status qaoa_get_info(qaoa_handle h, int32_t *n, int32_t *precision);
+
+/*
+ * Copy the cost diagonal C[0 .. 2^n) (Sec. IV-A, Eq. (2)) as fp64 into `out`.
+ * For QAOA_C64 handles the stored fp32 values are widened exactly.
+ *   out            fp64 [2^n], host or device memory
+ *   out_is_device  nonzero if `out` is device memory (copy is stream-ordered)
+ */
+qaoa_status qaoa_cost_diagonal(qaoa_handle h, double *out, int32_t out_is_device);
+
+/* Minimum and maximum of the cost diagonal (for approximation ratios). */
+qaoa_status qaoa_cost_extrema(qaoa_handle h, double *cmin, double *cmax);
+
+/*
+ * Prepare the QAOA state for angles gamma[p], beta[p] (Eq. (1); phase layer by
+ * Euler's formula, Sec. IV-B) and make it the handle's current state.
+ *   p             p >= 0 (p = 0 gives |+>^n)
+ *   gamma, beta   host fp64 [p], finite (may be NULL when p == 0)
+ *   out           NULL, or 2^n complex amplitudes (complex128 or complex64 per
+ *                 the handle's precision) receiving a copy of the state
+ *                 (Sec. IV-D: statevector export)
+ *   out_is_device nonzero if `out` is device memory
+ */
+qaoa_status qaoa_statevector(qaoa_handle h, int32_t p, const double *gamma, const double *beta,
+                             void *out, int32_t out_is_device);
+
+/* E = sum_z C[z] |psi_z|^2 of the current state (Sec. IV-D).  NO_STATE without one. */
+qaoa_status qaoa_expectation(qaoa_handle h, double *E);
+
+/*
+ * E(gamma, beta) in one fused sweep: the expectation is accumulated inside the
+ * last mixer pass instead of a separate reduction.  Leaves the state current.
+ */
+qaoa_status qaoa_evaluate(qaoa_handle h, int32_t p, const double *gamma, const double *beta,
+                          double *E);
+
+/*
+ * Expectation and its gradient with respect to all 2p angles by adjoint
+ * differentiation (Sec. II-B, Sec. IV-C): dE/dtheta_k = 2 Im <lam_k|H_k|phi_k>,
+ * where the layer states phi_k are recomputed by applying inverse layers to the
+ * final state (none are stored) and H_k is C or sum_j X_j.
+ *   E       host fp64 scalar (may be NULL)
+ *   dgamma  host fp64 [p]
+ *   dbeta   host fp64 [p]
+ * Allocates the adjoint vector on first use.  Consumes the state: afterwards
+ * the handle has no current state.
+ */
+qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const double *beta,
+                          double *E, double *dgamma, double *dbeta);
+
+/*
+ * Draw `shots` basis states from |psi_z|^2 of the current state and return
+ * each with its objective value (Sec. IV-D).  Shot s uses the uniform
+ * u_s = top 53 bits of Philox-4x32-10(counter = (s, 0), key = seed) * 2^-53 and
+ * returns the smallest z whose cumulative probability exceeds u_s * sum|psi|^2;
+ * a zero-probability state is never returned.  Results are in shot order and
+ * are deterministic for a given (state, seed).
+ *   z     uint64 [shots] receiving basis indices
+ *   cost  fp64 [shots] receiving C[z], or NULL
+ *   out_is_device  nonzero if z / cost are device memory
+ * Errors: NO_STATE; INVALID_ARGUMENT for shots < 0 or a zero-norm state.
+ */
+qaoa_status qaoa_sample(qaoa_handle h, int64_t shots, uint64_t seed, uint64_t *z, double *cost,
+                        int32_t out_is_device);
+
+/* Static English description of a status code. */
+const char *qaoa_status_string(qaoa_status s);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *qaoa_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QAOA_MI355X_QAOA_H */

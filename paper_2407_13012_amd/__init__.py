@@ -1,0 +1,34 @@
+"""QAOA statevector simulation on one AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding over ``libqaoa.so`` (C ABI in ``include/qaoa.h``): the
+functions below carry the C names and only marshal arguments; every step of
+the computation runs in the library's HIP kernels.  PyTorch is used for device
+memory (output tensors) and streams only.  If the shared library has not been
+built the binding raises at load time; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+from ._binding import (  # noqa: F401
+    QAOA_C128,
+    QAOA_C64,
+    QaoaError,
+    QaoaHandle,
+    library_path,
+    load_library,
+    qaoa_cost_diagonal,
+    qaoa_cost_extrema,
+    qaoa_create_maxcut,
+    qaoa_create_qubo,
+    qaoa_destroy,
+    qaoa_evaluate,
+    qaoa_expectation,
+    qaoa_get_info,
+    qaoa_gradient,
+    qaoa_last_error_message,
+    qaoa_sample,
+    qaoa_statevector,
+    qaoa_status_string,
+)
+
+__all__ = [name for name in dir() if name.startswith("qaoa_")] + [
+    "QaoaHandle", "QaoaError", "QAOA_C128", "QAOA_C64", "load_library", "library_path"]

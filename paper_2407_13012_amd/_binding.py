@@ -1,0 +1,299 @@
+"""ctypes marshalling for libqaoa.so.  Names follow the C ABI (include/qaoa.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+QAOA_C128 = 0
+QAOA_C64 = 1
+_PREC = {"c128": QAOA_C128, "complex128": QAOA_C128, QAOA_C128: QAOA_C128,
+         "c64": QAOA_C64, "complex64": QAOA_C64, QAOA_C64: QAOA_C64}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libqaoa.so")
+_lib: Optional[ctypes.CDLL] = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+class QaoaError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = load_library()
+        self.status = status
+        self.message = lib.qaoa_last_error_message().decode()
+        super().__init__(f"{where}: {lib.qaoa_status_string(status).decode()} ({self.message})")
+
+
+def load_library() -> ctypes.CDLL:
+    """Load the built HIP library.  Raises ImportError if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                          "`python paper_2407_13012_amd/build.py` (hipcc, gfx950)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    i32, i64, u64, d, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
+    pvp = ctypes.POINTER(ctypes.c_void_p)
+    pi32 = ctypes.POINTER(ctypes.c_int32)
+    pd = ctypes.POINTER(ctypes.c_double)
+    sigs = {
+        "qaoa_create_maxcut": [i32, i64, vp, vp, i32, vp, pvp],
+        "qaoa_create_qubo": [i32, i64, vp, vp, vp, d, i32, vp, pvp],
+        "qaoa_destroy": [vp],
+        "qaoa_get_info": [vp, pi32, pi32],
+        "qaoa_cost_diagonal": [vp, vp, i32],
+        "qaoa_cost_extrema": [vp, pd, pd],
+        "qaoa_statevector": [vp, i32, vp, vp, vp, i32],
+        "qaoa_expectation": [vp, pd],
+        "qaoa_evaluate": [vp, i32, vp, vp, pd],
+        "qaoa_gradient": [vp, i32, vp, vp, pd, vp, vp],
+        "qaoa_sample": [vp, i64, u64, vp, vp, i32],
+    }
+    for name, args in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.qaoa_status_string.argtypes = [ctypes.c_int]
+    lib.qaoa_status_string.restype = ctypes.c_char_p
+    lib.qaoa_last_error_message.argtypes = []
+    lib.qaoa_last_error_message.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        raise QaoaError(status, where)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _stream(stream):
+    """None -> torch's current HIP stream when a GPU is visible, else NULL."""
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _angles(gamma, beta):
+    g = np.ascontiguousarray(gamma, dtype=np.float64).reshape(-1)
+    b = np.ascontiguousarray(beta, dtype=np.float64).reshape(-1)
+    if g.shape != b.shape:
+        raise ValueError("gamma and beta must have the same length")
+    return g, b
+
+
+def _is_device_tensor(x) -> bool:
+    return hasattr(x, "is_cuda") and x.is_cuda
+
+
+# ---------------------------------------------------------------- C-named calls
+
+def qaoa_create_maxcut(n: int, edges, weights=None, precision="c128", stream=None):
+    lib = load_library()
+    e = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+    if w is not None and w.shape[0] != e.shape[0]:
+        raise ValueError("weights must have one entry per edge")
+    h = ctypes.c_void_p()
+    _check(lib.qaoa_create_maxcut(int(n), e.shape[0], _ptr(e), _ptr(w), _PREC[precision],
+                                  _stream(stream), ctypes.byref(h)), "qaoa_create_maxcut")
+    return h
+
+
+def qaoa_create_qubo(n: int, pairs, J, h=None, offset: float = 0.0, precision="c128", stream=None):
+    lib = load_library()
+    pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    Jv = np.ascontiguousarray(J, dtype=np.float64).reshape(-1)
+    if Jv.shape[0] != pr.shape[0]:
+        raise ValueError("J must have one entry per pair")
+    hv = None if h is None else np.ascontiguousarray(h, dtype=np.float64).reshape(-1)
+    if hv is not None and hv.shape[0] != n:
+        raise ValueError("h must have n entries")
+    out = ctypes.c_void_p()
+    _check(lib.qaoa_create_qubo(int(n), pr.shape[0], _ptr(pr), _ptr(Jv) if Jv.size else None,
+                                _ptr(hv), float(offset), _PREC[precision], _stream(stream),
+                                ctypes.byref(out)), "qaoa_create_qubo")
+    return out
+
+
+def qaoa_destroy(h) -> None:
+    _check(load_library().qaoa_destroy(h), "qaoa_destroy")
+
+
+def qaoa_get_info(h):
+    n, p = ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().qaoa_get_info(h, ctypes.byref(n), ctypes.byref(p)), "qaoa_get_info")
+    return n.value, p.value
+
+
+def qaoa_cost_diagonal(h, out=None):
+    """Return C as a numpy fp64 array, or fill `out` (numpy array or device tensor)."""
+    n, _ = qaoa_get_info(h)
+    lib = load_library()
+    if out is None:
+        out = np.empty(1 << n, dtype=np.float64)
+    if _is_device_tensor(out):
+        _check(lib.qaoa_cost_diagonal(h, ctypes.c_void_p(out.data_ptr()), 1), "qaoa_cost_diagonal")
+    else:
+        assert out.dtype == np.float64 and out.size == 1 << n and out.flags.c_contiguous
+        _check(lib.qaoa_cost_diagonal(h, _ptr(out), 0), "qaoa_cost_diagonal")
+    return out
+
+
+def qaoa_cost_extrema(h):
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().qaoa_cost_extrema(h, ctypes.byref(lo), ctypes.byref(hi)), "qaoa_cost_extrema")
+    return lo.value, hi.value
+
+
+def qaoa_statevector(h, gamma, beta, out=None, copy: bool = True):
+    """Prepare the state; return a copy (numpy or the given device tensor) unless copy=False."""
+    lib = load_library()
+    g, b = _angles(gamma, beta)
+    n, prec = qaoa_get_info(h)
+    if not copy:
+        _check(lib.qaoa_statevector(h, g.size, _ptr(g), _ptr(b), None, 0), "qaoa_statevector")
+        return None
+    if out is None:
+        out = np.empty(1 << n, dtype=np.complex64 if prec == QAOA_C64 else np.complex128)
+    if _is_device_tensor(out):
+        _check(lib.qaoa_statevector(h, g.size, _ptr(g), _ptr(b), ctypes.c_void_p(out.data_ptr()), 1),
+               "qaoa_statevector")
+    else:
+        _check(lib.qaoa_statevector(h, g.size, _ptr(g), _ptr(b), _ptr(out), 0), "qaoa_statevector")
+    return out
+
+
+def qaoa_expectation(h) -> float:
+    E = ctypes.c_double()
+    _check(load_library().qaoa_expectation(h, ctypes.byref(E)), "qaoa_expectation")
+    return E.value
+
+
+def qaoa_evaluate(h, gamma, beta) -> float:
+    g, b = _angles(gamma, beta)
+    E = ctypes.c_double()
+    _check(load_library().qaoa_evaluate(h, g.size, _ptr(g), _ptr(b), ctypes.byref(E)), "qaoa_evaluate")
+    return E.value
+
+
+def qaoa_gradient(h, gamma, beta):
+    """Return (E, dE/dgamma, dE/dbeta)."""
+    g, b = _angles(gamma, beta)
+    E = ctypes.c_double()
+    dg = np.zeros(g.size)
+    db = np.zeros(g.size)
+    _check(load_library().qaoa_gradient(h, g.size, _ptr(g), _ptr(b), ctypes.byref(E), _ptr(dg), _ptr(db)),
+           "qaoa_gradient")
+    return E.value, dg, db
+
+
+def qaoa_sample(h, shots: int, seed: int, z_out=None, cost_out=None, with_cost: bool = True):
+    """Draw shots from the current state.  Host numpy outputs by default; pass
+    device tensors (uint64-compatible int64 and float64) as z_out/cost_out to
+    keep the results on the GPU."""
+    lib = load_library()
+    if z_out is not None and _is_device_tensor(z_out):
+        cptr = ctypes.c_void_p(cost_out.data_ptr()) if cost_out is not None else None
+        _check(lib.qaoa_sample(h, int(shots), int(seed), ctypes.c_void_p(z_out.data_ptr()), cptr, 1),
+               "qaoa_sample")
+        return z_out, cost_out
+    m = max(int(shots), 0)  # a negative count is passed through for the library to reject
+    z = np.zeros(m, dtype=np.uint64) if z_out is None else z_out
+    c = (np.zeros(m, dtype=np.float64) if with_cost else None) if cost_out is None else cost_out
+    _check(lib.qaoa_sample(h, int(shots), int(seed) & (2**64 - 1), _ptr(z), _ptr(c), 0), "qaoa_sample")
+    return z, c
+
+
+def qaoa_status_string(status: int) -> str:
+    return load_library().qaoa_status_string(status).decode()
+
+
+def qaoa_last_error_message() -> str:
+    return load_library().qaoa_last_error_message().decode()
+
+
+# ---------------------------------------------------------------- convenience wrapper
+
+class QaoaHandle:
+    """Owning wrapper: ``with QaoaHandle.maxcut(n, edges, w) as q: q.gradient(g, b)``."""
+
+    def __init__(self, raw):
+        self._h = raw
+
+    @classmethod
+    def maxcut(cls, n, edges, weights=None, precision="c128", stream=None):
+        return cls(qaoa_create_maxcut(n, edges, weights, precision, stream))
+
+    @classmethod
+    def qubo(cls, n, pairs, J, h=None, offset=0.0, precision="c128", stream=None):
+        return cls(qaoa_create_qubo(n, pairs, J, h, offset, precision, stream))
+
+    @classmethod
+    def from_instance(cls, inst, precision="c128", stream=None):
+        if hasattr(inst, "edges"):
+            return cls.maxcut(inst.n, inst.edges, inst.weights, precision, stream)
+        return cls.qubo(inst.n, inst.pairs, inst.J, inst.h, inst.offset, precision, stream)
+
+    @property
+    def raw(self):
+        return self._h
+
+    @property
+    def n(self) -> int:
+        return qaoa_get_info(self._h)[0]
+
+    def close(self):
+        if self._h is not None:
+            qaoa_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def cost_diagonal(self, out=None):
+        return qaoa_cost_diagonal(self._h, out)
+
+    def cost_extrema(self):
+        return qaoa_cost_extrema(self._h)
+
+    def statevector(self, gamma: Sequence[float], beta: Sequence[float], out=None, copy=True):
+        return qaoa_statevector(self._h, gamma, beta, out, copy)
+
+    def expectation(self) -> float:
+        return qaoa_expectation(self._h)
+
+    def evaluate(self, gamma, beta) -> float:
+        return qaoa_evaluate(self._h, gamma, beta)
+
+    def gradient(self, gamma, beta):
+        return qaoa_gradient(self._h, gamma, beta)
+
+    def sample(self, shots: int, seed: int, **kw):
+        return qaoa_sample(self._h, shots, seed, **kw)

@@ -1,0 +1,643 @@
+// C ABI of the QAOA statevector library (declared in include/qaoa.h).
+//
+// Host runtime: argument validation (always before any HIP call), the handle
+// and its lazily allocated buffers (Sec. IV-B), the pass plan that groups the
+// n mixer rotations of a layer into tile passes, and the launch sequences for
+// the state, the expectation, the adjoint gradient and sampling.
+#include "qaoa.h"
+#include "qaoa_internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+void set_err(const char *fmt, const char *a = "", long long b = 0)
+{
+    char buf[512];
+    std::snprintf(buf, sizeof buf, fmt, a, b);
+    g_err = buf;
+}
+
+qaoa_status fail(qaoa_status st, const char *msg)
+{
+    g_err = msg;
+    return st;
+}
+
+}  // namespace
+
+struct qaoa_handle_s {
+    int n = 0;
+    int prec = QAOA_C128;
+    int device = 0;
+    uint64_t N = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void *psi = nullptr;   // state, 2^n amplitudes
+    void *lam = nullptr;   // adjoint vector, allocated on first gradient
+    void *cost = nullptr;  // cost diagonal, fp64 (c128) or fp32 (c64)
+    double *parts = nullptr;
+    size_t parts_cap = 0;  // doubles
+    double *res = nullptr;
+    size_t res_cap = 0;    // doubles
+    bool state_valid = false;
+    bool poisoned = false;
+    bool extrema_valid = false;
+    double cmin = 0, cmax = 0;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int old = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&old) != hipSuccess) {
+            ok = false;
+            return;
+        }
+        if (old != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard()
+    {
+        if (old >= 0) (void)hipSetDevice(old);
+    }
+};
+
+qaoa_status device_fail(qaoa_handle h, const char *what, hipError_t e)
+{
+    if (h) h->poisoned = true;
+    char buf[512];
+    std::snprintf(buf, sizeof buf, "%s failed: %s", what, hipGetErrorString(e));
+    g_err = buf;
+    return QAOA_ERR_DEVICE;
+}
+
+#define HIPCHECK(h, call)                                              \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) return device_fail((h), #call, e_);      \
+    } while (0)
+
+inline size_t amp_bytes(int prec) { return prec == QAOA_C64 ? 8 : 16; }
+inline size_t cost_bytes(int prec) { return prec == QAOA_C64 ? 4 : 8; }
+inline bool c64(const qaoa_handle h) { return h->prec == QAOA_C64; }
+inline uint64_t nblocks(int n) { return n <= qk::kTileBits ? 1ull : (1ull << (n - qk::kTileBits)); }
+
+qaoa_status check_handle(qaoa_handle h)
+{
+    if (!h) return fail(QAOA_ERR_INVALID_ARGUMENT, "handle is NULL");
+    if (h->poisoned) return fail(QAOA_ERR_DEVICE, "handle is unusable after an earlier device error");
+    return QAOA_OK;
+}
+
+qaoa_status check_angles(int32_t p, const double *gamma, const double *beta)
+{
+    if (p < 0) return fail(QAOA_ERR_INVALID_ARGUMENT, "p must be >= 0");
+    if (p > 0 && (!gamma || !beta)) return fail(QAOA_ERR_INVALID_ARGUMENT, "gamma/beta is NULL");
+    for (int i = 0; i < p; ++i)
+        if (!std::isfinite(gamma[i]) || !std::isfinite(beta[i]))
+            return fail(QAOA_ERR_INVALID_ARGUMENT, "angles must be finite");
+    return QAOA_OK;
+}
+
+qaoa_status check_terms(int32_t n, int64_t m, const int32_t *idx, const double *w, bool w_required)
+{
+    if (n < 1 || n > QAOA_MAX_QUBITS)
+        return fail(QAOA_ERR_INVALID_ARGUMENT, "n must be in [1, QAOA_MAX_QUBITS]");
+    if (m < 0) return fail(QAOA_ERR_INVALID_ARGUMENT, "m must be >= 0");
+    if (m > 0 && !idx) return fail(QAOA_ERR_INVALID_ARGUMENT, "index array is NULL");
+    if (m > 0 && w_required && !w) return fail(QAOA_ERR_INVALID_ARGUMENT, "weight array is NULL");
+    for (int64_t k = 0; k < m; ++k) {
+        const int32_t i = idx[2 * k], j = idx[2 * k + 1];
+        if (i < 0 || i >= n || j < 0 || j >= n) {
+            set_err("term %s%lld has a variable index outside [0, n)", "", (long long)k);
+            return QAOA_ERR_INVALID_ARGUMENT;
+        }
+        if (i == j) {
+            set_err("term %s%lld joins a variable to itself", "", (long long)k);
+            return QAOA_ERR_INVALID_ARGUMENT;
+        }
+        if (w && !std::isfinite(w[k])) return fail(QAOA_ERR_INVALID_ARGUMENT, "weights must be finite");
+    }
+    return QAOA_OK;
+}
+
+// Ensure `*buf` holds at least `count` doubles.
+qaoa_status ensure_doubles(qaoa_handle h, double **buf, size_t *cap, size_t count)
+{
+    if (*cap >= count) return QAOA_OK;
+    if (*buf) HIPCHECK(h, hipFree(*buf));
+    *buf = nullptr;
+    *cap = 0;
+    size_t fr = 0, tot = 0;
+    HIPCHECK(h, hipMemGetInfo(&fr, &tot));
+    if (count * sizeof(double) > fr) return fail(QAOA_ERR_OUT_OF_MEMORY, "scratch buffer does not fit");
+    HIPCHECK(h, hipMalloc((void **)buf, count * sizeof(double)));
+    *cap = count;
+    return QAOA_OK;
+}
+
+// Mixer groups of a layer: the low group covers bits [0, 12) (or all n < 12
+// bits); the remaining n-12 qubits are split into nearly equal high groups of
+// at most 10, each tile keeping 12-k low bits as contiguous spectators.
+std::vector<qk::Group> make_groups(int n)
+{
+    std::vector<qk::Group> g;
+    if (n <= qk::kTileBits) {
+        g.push_back({0, 0, n});
+        return g;
+    }
+    g.push_back({0, 0, qk::kTileBits});
+    const int r = n - qk::kTileBits, P = (r + 9) / 10;
+    int h = qk::kTileBits;
+    for (int i = 0; i < P; ++i) {
+        const int k = r / P + (i < r % P ? 1 : 0);
+        g.push_back({qk::kTileBits - k, h, k});
+        h += k;
+    }
+    return g;
+}
+
+qk::PassArgs pass_args(qaoa_handle h, const qk::Group &g)
+{
+    qk::PassArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.psi = h->psi;
+    a.lam = h->lam;
+    a.cost = h->cost;
+    a.S = (uint32_t)g.S;
+    a.h = (uint32_t)g.h;
+    a.ta_bits = (uint32_t)(g.h - g.S);
+    a.tb_shift = (uint32_t)(g.h + g.k);
+    a.tbits = (uint32_t)(h->n < qk::kTileBits ? h->n : qk::kTileBits);
+    a.xcd_remap = (nblocks(h->n) % 32 == 0) ? 1u : 0u;
+    a.amp0 = 1.0 / std::sqrt((double)h->N);
+    return a;
+}
+
+qaoa_status run_pass(qaoa_handle h, int mode, const qk::PassArgs &a)
+{
+    HIPCHECK(h, qk::launch_pass(mode, c64(h), a, nblocks(h->n), h->stream));
+    return QAOA_OK;
+}
+
+// Forward evolution through layers [0, p); the last `skip_last` groups of the
+// last layer are left out (the gradient's turn pass runs the last group).
+// With `e_out`, the final pass accumulates E into partial slot 0.
+qaoa_status run_forward(qaoa_handle h, int p, const double *gamma, const double *beta,
+                        bool skip_last, bool e_out)
+{
+    const std::vector<qk::Group> G = make_groups(h->n);
+    const int P = (int)G.size();
+    for (int l = 0; l < p; ++l) {
+        const int gend = (l == p - 1 && skip_last) ? P - 1 : P;
+        for (int gi = 0; gi < gend; ++gi) {
+            qk::PassArgs a = pass_args(h, G[gi]);
+            a.cm = std::cos(beta[l]);
+            a.sm = std::sin(beta[l]);
+            if (gi == 0) {
+                a.flags |= qk::kPhaseIn;
+                a.gamma_in = gamma[l];
+                if (l == 0) a.flags |= qk::kInit;
+            }
+            if (e_out && l == p - 1 && gi == gend - 1) {
+                a.flags |= qk::kEOut;
+                a.part_e = h->parts;
+            }
+            qaoa_status st = run_pass(h, qk::kFwd, a);
+            if (st != QAOA_OK) return st;
+        }
+    }
+    return QAOA_OK;
+}
+
+qaoa_status fetch_results(qaoa_handle h, int nslots, uint64_t count, double *host)
+{
+    HIPCHECK(h, qk::launch_sum_slots(h->parts, count, count, nslots, h->res, h->stream));
+    HIPCHECK(h, hipMemcpyAsync(host, h->res, (size_t)nslots * sizeof(double), hipMemcpyDeviceToHost,
+                               h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    return QAOA_OK;
+}
+
+qaoa_status create_common(int32_t n, int32_t precision, void *stream, qaoa_handle *out,
+                          qaoa_handle *hh)
+{
+    if (!out) return fail(QAOA_ERR_INVALID_ARGUMENT, "out is NULL");
+    if (precision != QAOA_C128 && precision != QAOA_C64)
+        return fail(QAOA_ERR_INVALID_ARGUMENT, "unknown precision");
+    qaoa_handle h = new (std::nothrow) qaoa_handle_s();
+    if (!h) return fail(QAOA_ERR_OUT_OF_MEMORY, "host allocation failed");
+    h->n = n;
+    h->prec = precision;
+    h->N = 1ull << n;
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return device_fail(nullptr, "hipGetDevice", e);
+    }
+    size_t fr = 0, tot = 0;
+    e = hipMemGetInfo(&fr, &tot);
+    if (e != hipSuccess) {
+        delete h;
+        return device_fail(nullptr, "hipMemGetInfo", e);
+    }
+    const double need = (double)h->N * (double)(amp_bytes(precision) + cost_bytes(precision)) +
+                        (double)nblocks(n) * 8.0 * 2 + (1 << 20);
+    if (need > (double)fr) {
+        delete h;
+        return fail(QAOA_ERR_OUT_OF_MEMORY, "state and cost diagonal do not fit in free device memory");
+    }
+    if (stream) {
+        h->stream = (hipStream_t)stream;
+    } else {
+        e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete h;
+            return device_fail(nullptr, "hipStreamCreateWithFlags", e);
+        }
+        h->own_stream = true;
+    }
+    *hh = h;
+    if ((e = hipMalloc(&h->psi, h->N * amp_bytes(precision))) != hipSuccess ||
+        (e = hipMalloc(&h->cost, h->N * cost_bytes(precision))) != hipSuccess) {
+        qaoa_destroy(h);
+        *hh = nullptr;
+        return device_fail(nullptr, "hipMalloc", e);
+    }
+    qaoa_status st = ensure_doubles(h, &h->parts, &h->parts_cap, 2 * nblocks(n) + 2);
+    if (st == QAOA_OK) st = ensure_doubles(h, &h->res, &h->res_cap, 64);
+    if (st != QAOA_OK) {
+        std::string keep = g_err;
+        qaoa_destroy(h);
+        *hh = nullptr;
+        g_err = keep;
+        return st;
+    }
+    return QAOA_OK;
+}
+
+// Copies host term arrays to the device, builds the cost diagonal, frees the copies.
+template <typename Launch>
+qaoa_status build_cost(qaoa_handle h, const std::vector<std::pair<const void *, size_t>> &arrays,
+                       Launch launch)
+{
+    std::vector<void *> dev(arrays.size(), nullptr);
+    qaoa_status st = QAOA_OK;
+    for (size_t i = 0; i < arrays.size() && st == QAOA_OK; ++i) {
+        if (!arrays[i].first || arrays[i].second == 0) continue;
+        hipError_t e = hipMalloc(&dev[i], arrays[i].second);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dev[i], arrays[i].first, arrays[i].second, hipMemcpyHostToDevice,
+                               h->stream);
+        if (e != hipSuccess) st = device_fail(h, "term upload", e);
+    }
+    if (st == QAOA_OK) {
+        hipError_t e = launch(dev);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) st = device_fail(h, "cost diagonal", e);
+    }
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+qaoa_status qaoa_create_maxcut(int32_t n, int64_t m, const int32_t *edges, const double *w,
+                               int32_t precision, void *stream, qaoa_handle *out)
+{
+    qaoa_status st = check_terms(n, m, edges, w, false);
+    if (st != QAOA_OK) return st;
+    qaoa_handle h = nullptr;
+    if ((st = create_common(n, precision, stream, out, &h)) != QAOA_OK) return st;
+    st = build_cost(h, {{edges, (size_t)m * 2 * sizeof(int32_t)}, {w, w ? (size_t)m * sizeof(double) : 0}},
+                    [&](std::vector<void *> &d) {
+                        return qk::launch_cost_maxcut(c64(h), h->cost, n, m, (const int32_t *)d[0],
+                                                      (const double *)d[1], h->stream);
+                    });
+    if (st != QAOA_OK) {
+        std::string keep = g_err;
+        qaoa_destroy(h);
+        g_err = keep;
+        return st;
+    }
+    *out = h;
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_create_qubo(int32_t n, int64_t m, const int32_t *pairs, const double *J,
+                             const double *hl, double offset, int32_t precision, void *stream,
+                             qaoa_handle *out)
+{
+    qaoa_status st = check_terms(n, m, pairs, J, true);
+    if (st != QAOA_OK) return st;
+    if (!std::isfinite(offset)) return fail(QAOA_ERR_INVALID_ARGUMENT, "offset must be finite");
+    if (hl)
+        for (int i = 0; i < n; ++i)
+            if (!std::isfinite(hl[i])) return fail(QAOA_ERR_INVALID_ARGUMENT, "h must be finite");
+    qaoa_handle h = nullptr;
+    if ((st = create_common(n, precision, stream, out, &h)) != QAOA_OK) return st;
+    st = build_cost(h,
+                    {{pairs, (size_t)m * 2 * sizeof(int32_t)},
+                     {J, (size_t)m * sizeof(double)},
+                     {hl, hl ? (size_t)n * sizeof(double) : 0}},
+                    [&](std::vector<void *> &d) {
+                        return qk::launch_cost_qubo(c64(h), h->cost, n, m, (const int32_t *)d[0],
+                                                    (const double *)d[1], (const double *)d[2],
+                                                    offset, h->stream);
+                    });
+    if (st != QAOA_OK) {
+        std::string keep = g_err;
+        qaoa_destroy(h);
+        g_err = keep;
+        return st;
+    }
+    *out = h;
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_destroy(qaoa_handle h)
+{
+    if (!h) return QAOA_OK;
+    DeviceGuard dg(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->psi) (void)hipFree(h->psi);
+    if (h->lam) (void)hipFree(h->lam);
+    if (h->cost) (void)hipFree(h->cost);
+    if (h->parts) (void)hipFree(h->parts);
+    if (h->res) (void)hipFree(h->res);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_get_info(qaoa_handle h, int32_t *n, int32_t *precision)
+{
+    if (!h) return fail(QAOA_ERR_INVALID_ARGUMENT, "handle is NULL");
+    if (n) *n = h->n;
+    if (precision) *precision = h->prec;
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_cost_diagonal(qaoa_handle h, double *out, int32_t out_is_device)
+{
+    qaoa_status st = check_handle(h);
+    if (st != QAOA_OK) return st;
+    if (!out) return fail(QAOA_ERR_INVALID_ARGUMENT, "out is NULL");
+    DeviceGuard dg(h->device);
+    if (!c64(h)) {
+        HIPCHECK(h, hipMemcpyAsync(out, h->cost, h->N * 8,
+                                   out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                   h->stream));
+        if (!out_is_device) HIPCHECK(h, hipStreamSynchronize(h->stream));
+        return QAOA_OK;
+    }
+    if (out_is_device) {
+        HIPCHECK(h, qk::launch_widen_cost((const float *)h->cost, out, h->N, h->stream));
+        return QAOA_OK;
+    }
+    std::vector<float> tmp;
+    try {
+        tmp.resize(h->N);
+    } catch (...) {
+        return fail(QAOA_ERR_OUT_OF_MEMORY, "host staging buffer");
+    }
+    HIPCHECK(h, hipMemcpyAsync(tmp.data(), h->cost, h->N * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    for (uint64_t z = 0; z < h->N; ++z) out[z] = (double)tmp[z];
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_cost_extrema(qaoa_handle h, double *cmin, double *cmax)
+{
+    qaoa_status st = check_handle(h);
+    if (st != QAOA_OK) return st;
+    if (!cmin || !cmax) return fail(QAOA_ERR_INVALID_ARGUMENT, "output is NULL");
+    if (!h->extrema_valid) {
+        DeviceGuard dg(h->device);
+        const uint64_t T = (h->N + qk::kTile - 1) / qk::kTile;
+        if ((st = ensure_doubles(h, &h->parts, &h->parts_cap, 2 * T)) != QAOA_OK) return st;
+        HIPCHECK(h, qk::launch_minmax(c64(h), h->cost, h->n, h->parts, h->parts + T, h->stream));
+        HIPCHECK(h, qk::launch_minmax_final(h->parts, h->parts + T, T, h->res, h->stream));
+        double r[2];
+        HIPCHECK(h, hipMemcpyAsync(r, h->res, sizeof r, hipMemcpyDeviceToHost, h->stream));
+        HIPCHECK(h, hipStreamSynchronize(h->stream));
+        h->cmin = r[0];
+        h->cmax = r[1];
+        h->extrema_valid = true;
+    }
+    *cmin = h->cmin;
+    *cmax = h->cmax;
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_statevector(qaoa_handle h, int32_t p, const double *gamma, const double *beta,
+                             void *out, int32_t out_is_device)
+{
+    qaoa_status st = check_handle(h);
+    if (st != QAOA_OK) return st;
+    if ((st = check_angles(p, gamma, beta)) != QAOA_OK) return st;
+    DeviceGuard dg(h->device);
+    h->state_valid = false;
+    if (p == 0) {
+        HIPCHECK(h, qk::launch_fill_plus(c64(h), h->psi, h->n, h->stream));
+    } else if ((st = run_forward(h, p, gamma, beta, false, false)) != QAOA_OK) {
+        return st;
+    }
+    h->state_valid = true;
+    if (out) {
+        HIPCHECK(h, hipMemcpyAsync(out, h->psi, h->N * amp_bytes(h->prec),
+                                   out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                   h->stream));
+        if (!out_is_device) HIPCHECK(h, hipStreamSynchronize(h->stream));
+    }
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_expectation(qaoa_handle h, double *E)
+{
+    qaoa_status st = check_handle(h);
+    if (st != QAOA_OK) return st;
+    if (!E) return fail(QAOA_ERR_INVALID_ARGUMENT, "E is NULL");
+    if (!h->state_valid) return fail(QAOA_ERR_NO_STATE, "no current state");
+    DeviceGuard dg(h->device);
+    const uint64_t T = (h->N + qk::kTile - 1) / qk::kTile;
+    if ((st = ensure_doubles(h, &h->parts, &h->parts_cap, T)) != QAOA_OK) return st;
+    HIPCHECK(h, qk::launch_expect(c64(h), h->psi, h->cost, h->n, h->parts, h->stream));
+    return fetch_results(h, 1, T, E);
+}
+
+qaoa_status qaoa_evaluate(qaoa_handle h, int32_t p, const double *gamma, const double *beta,
+                          double *E)
+{
+    qaoa_status st = check_handle(h);
+    if (st != QAOA_OK) return st;
+    if ((st = check_angles(p, gamma, beta)) != QAOA_OK) return st;
+    if (!E) return fail(QAOA_ERR_INVALID_ARGUMENT, "E is NULL");
+    if (p == 0) {
+        if ((st = qaoa_statevector(h, 0, nullptr, nullptr, nullptr, 0)) != QAOA_OK) return st;
+        return qaoa_expectation(h, E);
+    }
+    DeviceGuard dg(h->device);
+    h->state_valid = false;
+    const uint64_t T = nblocks(h->n);
+    if ((st = ensure_doubles(h, &h->parts, &h->parts_cap, T)) != QAOA_OK) return st;
+    if ((st = run_forward(h, p, gamma, beta, false, true)) != QAOA_OK) return st;
+    h->state_valid = true;
+    return fetch_results(h, 1, T, E);
+}
+
+qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const double *beta,
+                          double *E, double *dgamma, double *dbeta)
+{
+    qaoa_status st = check_handle(h);
+    if (st != QAOA_OK) return st;
+    if ((st = check_angles(p, gamma, beta)) != QAOA_OK) return st;
+    if (p > 0 && (!dgamma || !dbeta)) return fail(QAOA_ERR_INVALID_ARGUMENT, "gradient output is NULL");
+    if (p == 0) {
+        double e0;
+        if ((st = qaoa_evaluate(h, 0, nullptr, nullptr, &e0)) != QAOA_OK) return st;
+        if (E) *E = e0;
+        h->state_valid = false;
+        return QAOA_OK;
+    }
+    DeviceGuard dg(h->device);
+    if (!h->lam) {
+        size_t fr = 0, tot = 0;
+        HIPCHECK(h, hipMemGetInfo(&fr, &tot));
+        if (h->N * amp_bytes(h->prec) > fr)
+            return fail(QAOA_ERR_OUT_OF_MEMORY, "adjoint vector does not fit in free device memory");
+        HIPCHECK(h, hipMalloc(&h->lam, h->N * amp_bytes(h->prec)));
+    }
+    const uint64_t T = nblocks(h->n);
+    const int nslots = 2 * p + 1;
+    if ((st = ensure_doubles(h, &h->parts, &h->parts_cap, (size_t)nslots * T)) != QAOA_OK) return st;
+    if ((st = ensure_doubles(h, &h->res, &h->res_cap, (size_t)nslots)) != QAOA_OK) return st;
+    h->state_valid = false;
+
+    const std::vector<qk::Group> G = make_groups(h->n);
+    const int P = (int)G.size();
+    double *slotE = h->parts;
+    auto slotB = [&](int l) { return h->parts + (uint64_t)(1 + l) * T; };
+    auto slotG = [&](int l) { return h->parts + (uint64_t)(1 + p + l) * T; };
+
+    // Forward through every group except the last group of the last layer.
+    if ((st = run_forward(h, p, gamma, beta, true, false)) != QAOA_OK) return st;
+
+    // Turn pass: last group of layer p-1 forward, E, lam = C phi, group undone on lam.
+    {
+        const int l = p - 1;
+        qk::PassArgs a = pass_args(h, G[P - 1]);
+        a.cm = std::cos(beta[l]);
+        a.sm = std::sin(beta[l]);
+        a.cu = a.cm;
+        a.su = -a.sm;
+        a.part_e = slotE;
+        a.part_b = slotB(l);
+        if (P == 1) {
+            a.flags |= qk::kPhaseIn | qk::kPhaseOut;
+            a.gamma_in = a.gamma_out = gamma[l];
+            a.part_g = slotG(l);
+            if (l == 0) a.flags |= qk::kInit | qk::kNoStore;
+        }
+        if ((st = run_pass(h, qk::kTurn, a)) != QAOA_OK) return st;
+    }
+    // Backward sweep: layer l undoes groups (last..0); group 0 also undoes the phase.
+    for (int l = p - 1; l >= 0; --l) {
+        const int gstart = (l == p - 1) ? P - 2 : P - 1;
+        for (int gi = gstart; gi >= 0; --gi) {
+            qk::PassArgs a = pass_args(h, G[gi]);
+            a.cu = std::cos(beta[l]);
+            a.su = -std::sin(beta[l]);
+            a.part_b = slotB(l);
+            // The first pass of a layer's sweep writes the beta partial (the turn
+            // pass does so for layer p-1); later passes add to it.
+            if (l == p - 1 || gi != P - 1) a.flags |= qk::kBetaAcc;
+            if (gi == 0) {
+                a.flags |= qk::kPhaseOut;
+                a.gamma_out = gamma[l];
+                a.part_g = slotG(l);
+                if (l == 0) a.flags |= qk::kNoStore;
+            }
+            if ((st = run_pass(h, qk::kBwd, a)) != QAOA_OK) return st;
+        }
+    }
+    std::vector<double> r((size_t)nslots);
+    if ((st = fetch_results(h, nslots, T, r.data())) != QAOA_OK) return st;
+    if (E) *E = r[0];
+    for (int l = 0; l < p; ++l) {
+        dbeta[l] = 2.0 * r[1 + l];
+        dgamma[l] = 2.0 * r[1 + p + l];
+    }
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_sample(qaoa_handle h, int64_t shots, uint64_t seed, uint64_t *z, double *cost,
+                        int32_t out_is_device)
+{
+    qaoa_status st = check_handle(h);
+    if (st != QAOA_OK) return st;
+    if (shots < 0) return fail(QAOA_ERR_INVALID_ARGUMENT, "shots must be >= 0");
+    if (shots > 0 && !z) return fail(QAOA_ERR_INVALID_ARGUMENT, "z is NULL");
+    if (!h->state_valid) return fail(QAOA_ERR_NO_STATE, "no current state");
+    if (shots == 0) return QAOA_OK;
+    DeviceGuard dg(h->device);
+    const int sbits = qk::sample_subblock_bits(h->n);
+    const uint64_t nsub = h->N >> sbits;
+    const uint64_t nscr = qk::scan_scratch_doubles(nsub);
+    // layout: sub[nsub] | pre[nsub + 1] | scratch[nscr] | (host output staging)
+    const size_t base = 2 * nsub + 1 + nscr;
+    const size_t stage = out_is_device ? 0 : (size_t)shots * 2;
+    if ((st = ensure_doubles(h, &h->parts, &h->parts_cap, base + stage)) != QAOA_OK) return st;
+    double *sub = h->parts, *pre = sub + nsub, *scr = pre + nsub + 1;
+    HIPCHECK(h, qk::launch_submass(c64(h), h->psi, h->n, sbits, sub, h->stream));
+    HIPCHECK(h, qk::launch_exclusive_scan(sub, nsub, pre, scr, h->stream));
+    double T = 0;
+    HIPCHECK(h, hipMemcpyAsync(&T, pre + nsub, sizeof T, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(QAOA_ERR_INVALID_ARGUMENT, "state has zero norm");
+    uint64_t *dz = z;
+    double *dc = cost;
+    if (!out_is_device) {
+        dz = (uint64_t *)(h->parts + base);
+        dc = cost ? h->parts + base + shots : nullptr;
+    }
+    HIPCHECK(h, qk::launch_shots(c64(h), h->psi, h->cost, h->n, sbits, pre, nsub, shots, seed, dz,
+                                 dc, h->stream));
+    if (!out_is_device) {
+        HIPCHECK(h, hipMemcpyAsync(z, dz, (size_t)shots * 8, hipMemcpyDeviceToHost, h->stream));
+        if (cost)
+            HIPCHECK(h, hipMemcpyAsync(cost, dc, (size_t)shots * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHECK(h, hipStreamSynchronize(h->stream));
+    }
+    return QAOA_OK;
+}
+
+const char *qaoa_status_string(qaoa_status s)
+{
+    switch (s) {
+    case QAOA_OK: return "success";
+    case QAOA_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case QAOA_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case QAOA_ERR_DEVICE: return "device error";
+    case QAOA_ERR_NO_STATE: return "no current state";
+    case QAOA_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *qaoa_last_error_message(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared
+entry point, and rejects invalid arguments before touching the GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qaoa.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(qaoa_\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2407_13012_amd import load_library
+    try:
+        return load_library()
+    except ImportError as e:
+        pytest.fail(str(e))
+
+
+def test_header_declares_expected_calls():
+    names = declared_functions()
+    for want in ["qaoa_create_maxcut", "qaoa_create_qubo", "qaoa_destroy", "qaoa_cost_diagonal",
+                 "qaoa_statevector", "qaoa_expectation", "qaoa_gradient", "qaoa_sample",
+                 "qaoa_status_string", "qaoa_last_error_message", "qaoa_evaluate",
+                 "qaoa_cost_extrema", "qaoa_get_info"]:
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2407_13012_amd import library_path
+    out = subprocess.run(["nm", "-D", "--defined-only", library_path()], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    for f in declared_functions():
+        getattr(lib, f)
+
+
+def test_library_is_gfx950_code_object():
+    from paper_2407_13012_amd import library_path
+    data = open(library_path(), "rb").read()
+    assert b"gfx950" in data
+
+
+def test_status_strings(lib):
+    lib.qaoa_status_string.restype = ctypes.c_char_p
+    assert lib.qaoa_status_string(0) == b"success"
+    assert lib.qaoa_status_string(1) == b"invalid argument"
+    assert lib.qaoa_status_string(99) == b"unknown status"
+
+
+def _create_maxcut(lib, n, edges, w=None, prec=0, out=True):
+    e = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    h = ctypes.c_void_p()
+    wp = None if w is None else np.ascontiguousarray(w, dtype=np.float64).ctypes.data
+    return lib.qaoa_create_maxcut(n, e.shape[0], e.ctypes.data if e.size else None, wp, prec, None,
+                                  ctypes.byref(h) if out else None)
+
+
+@pytest.mark.parametrize("n,edges,w,prec", [
+    (0, [[0, 1]], None, 0),              # n too small
+    (41, [[0, 1]], None, 0),             # n too large
+    (4, [[0, 4]], None, 0),              # index out of range
+    (4, [[-1, 2]], None, 0),             # negative index
+    (4, [[2, 2]], None, 0),              # self-loop
+    (4, [[0, 1]], [float("nan")], 0),    # non-finite weight
+    (4, [[0, 1]], [float("inf")], 0),
+    (4, [[0, 1]], None, 7),              # unknown precision
+])
+def test_create_maxcut_rejects(lib, n, edges, w, prec):
+    assert _create_maxcut(lib, n, edges, w, prec) == 1
+    lib.qaoa_last_error_message.restype = ctypes.c_char_p
+    assert lib.qaoa_last_error_message() != b""
+
+
+def test_create_rejects_null_out_and_negative_m(lib):
+    assert _create_maxcut(lib, 3, [[0, 1]], out=False) == 1
+    h = ctypes.c_void_p()
+    assert lib.qaoa_create_maxcut(3, -1, None, None, 0, None, ctypes.byref(h)) == 1
+    assert lib.qaoa_create_maxcut(3, 2, None, None, 0, None, ctypes.byref(h)) == 1
+
+
+def test_create_qubo_rejects(lib):
+    h = ctypes.c_void_p()
+    pr = np.array([[0, 1]], dtype=np.int32)
+    J = np.array([1.0])
+    hb = np.array([0.0, np.nan, 0.0])
+    # J missing for m > 0
+    assert lib.qaoa_create_qubo(3, 1, pr.ctypes.data, None, None, ctypes.c_double(0.0), 0, None,
+                                ctypes.byref(h)) == 1
+    # non-finite h
+    assert lib.qaoa_create_qubo(3, 1, pr.ctypes.data, J.ctypes.data, hb.ctypes.data,
+                                ctypes.c_double(0.0), 0, None, ctypes.byref(h)) == 1
+    # non-finite offset
+    assert lib.qaoa_create_qubo(3, 1, pr.ctypes.data, J.ctypes.data, None,
+                                ctypes.c_double(float("nan")), 0, None, ctypes.byref(h)) == 1
+
+
+def test_calls_reject_null_handle(lib):
+    d = ctypes.c_double()
+    g = np.zeros(1)
+    assert lib.qaoa_destroy(None) == 0
+    assert lib.qaoa_expectation(None, ctypes.byref(d)) == 1
+    assert lib.qaoa_cost_diagonal(None, g.ctypes.data, 0) == 1
+    assert lib.qaoa_cost_extrema(None, ctypes.byref(d), ctypes.byref(d)) == 1
+    assert lib.qaoa_statevector(None, 1, g.ctypes.data, g.ctypes.data, None, 0) == 1
+    assert lib.qaoa_evaluate(None, 1, g.ctypes.data, g.ctypes.data, ctypes.byref(d)) == 1
+    assert lib.qaoa_gradient(None, 1, g.ctypes.data, g.ctypes.data, None, g.ctypes.data,
+                             g.ctypes.data) == 1
+    assert lib.qaoa_sample(None, 10, 0, g.ctypes.data, None, 0) == 1
+    assert lib.qaoa_get_info(None, None, None) == 1
+
+
+def test_valid_create_without_gpu_reports_device_error(lib):
+    """In a container without a GPU a valid request passes validation and then
+    fails at the first HIP call with QAOA_ERR_DEVICE (never a crash)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert _create_maxcut(lib, 4, [[0, 1], [1, 2]]) == 3
+
+
+def test_python_binding_has_c_names():
+    import paper_2407_13012_amd as pkg
+    for f in declared_functions():
+        assert hasattr(pkg, f), f
