@@ -1,0 +1,227 @@
+#!/usr/bin/env python
+"""Throughput of QAOA expectation + adjoint gradient on one MI355X.
+
+Workload: 0-1 QUBO on n = 32 variables with an Erdos-Renyi(0.1) coupling
+pattern, J_ij ~ N(0,1), h_i ~ N(0,1) (seed 2), depth p = 3, angles = linear
+ramp + N(0, 0.05) noise; complex128 state (64 GiB) + adjoint vector (64 GiB)
++ fp64 cost diagonal (32 GiB), all resident in HBM.  One step = one call of
+qaoa_gradient: E and all 2p partial derivatives.
+
+Prints one JSON line.  Besides the headline throughput it reports the
+roofline of the dominant kernel (HIP events bracketing every pass launch on the
+library's stream, divided into the pass's algorithmic bytes) and the CPU
+oracle's throughput on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grad evals/s + HBM GB/s at n=32 p=3; time-to-ratio learned vs plain init"
+HBM_PEAK_GBS = 8000.0
+
+
+def model_bytes_per_amp(n: int, p: int, s: int, c: int) -> float:
+    """Per-amplitude bytes of one E+G under the pass model p(6 P s + 2 c) + c - 2 s
+    with P = ceil(n / kmax) passes per mixer layer (kmax = 13 for 16-byte
+    amplitudes, 14 for 8-byte ones)."""
+    kmax = 13 if s == 16 else 14
+    P = math.ceil(n / kmax)
+    return p * (6 * P * s + 2 * c) + c - 2 * s
+
+
+def time_gradients(q, gamma, beta, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        q.gradient(gamma, beta)
+    torch.cuda.synchronize()
+    q.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        q.gradient(gamma, beta)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = q.profile_read()
+    q.profile_enable(False)
+    return t1 - t0, prof
+
+
+def cpu_baseline(inst_fn, p_n, full_n, gamma, beta):
+    import oracle
+    inst = inst_fn(p_n)["instance"]
+    C = oracle.cost_of(inst)
+    t0 = time.perf_counter()
+    oracle.gradient(p_n, C, gamma, beta)
+    dt = time.perf_counter() - t0
+    scale = 2.0 ** (full_n - p_n)
+    return {
+        "value": 1.0 / (dt * scale),
+        "unit": "grad_evals/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"one oracle E+G ({dt:.2f} s) of the n={p_n} member of the same QUBO family "
+                   f"(p={len(gamma)}), scaled by 2^{full_n - p_n} to n={full_n} (extrapolated)"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--precision", default="c128", choices=["c128", "c64"])
+    ap.add_argument("--cpu-sample-n", type=int, default=26)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="first run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one MI355X only: the simulator runs each instance on a single "
+              "GPU and no multi-GPU path is built; run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import qaoa_inputs as qi
+    from paper_2407_13012_amd import QaoaHandle
+
+    torch.cuda.set_device(0)
+    if args.copy_probe_gib > 0:
+        nel = int(args.copy_probe_gib * (1 << 30)) // 8
+        x = torch.empty(nel, dtype=torch.float64, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(f"[copy-probe] {nel * 8} bytes read, {nel * 8} bytes written", file=sys.stderr, flush=True)
+        del x, y
+        torch.cuda.empty_cache()
+
+    w = qi.workload_qubo32(args.n)
+    inst, gamma, beta = w["instance"], w["gamma"], w["beta"]
+    p = len(gamma)
+    s = 16 if args.precision == "c128" else 8
+    c = 8 if args.precision == "c128" else 4
+    print(f"[bench] n={args.n} p={p} m={inst.m} precision={args.precision}", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    q = QaoaHandle.from_instance(inst, args.precision)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    dt, prof = time_gradients(q, gamma, beta, args.steps, args.warmup)
+    ms_per_step = 1e3 * dt / args.steps
+    value = args.steps / dt
+    print(f"[bench] {args.steps} steps in {dt:.3f} s ({ms_per_step:.1f} ms/step)", file=sys.stderr, flush=True)
+
+    kinds = {k: {"launches": v[0], "ms": v[1], "bytes": v[2],
+                 "gbs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
+             for k, v in prof.items()}
+    dom = max(kinds, key=lambda k: kinds[k]["ms"])
+    dk = kinds[dom]
+    achieved = dk["gbs"]
+    total_bytes = sum(v["bytes"] for v in kinds.values()) / args.steps
+    kernel_ms = sum(v["ms"] for v in kinds.values()) / args.steps
+    roofline = {
+        "bound": "hbm",
+        "kernel": f"k_pass<{'double' if s == 16 else 'float'}, {dom}>",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": None,
+        "bytes_per_launch": dk["bytes"] / max(dk["launches"], 1),
+        "avg_launch_ms": dk["ms"] / max(dk["launches"], 1),
+    }
+    N = 2.0 ** args.n
+    extra = {
+        "passes": kinds,
+        "algorithmic_bytes_per_step": total_bytes,
+        "pass_time_ms_per_step": kernel_ms,
+        "step_GBps": total_bytes / (ms_per_step * 1e-3) / 1e9,
+        "model_bytes_per_amp": model_bytes_per_amp(args.n, p, s, c),
+        "model_roofline_frac": model_bytes_per_amp(args.n, p, s, c) * N / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "create_s": t_create,
+    }
+    E, dg, db = q.gradient(gamma, beta)
+    extra["E"] = E
+    extra["grad_norm_inf"] = float(max(np.abs(dg).max(), np.abs(db).max()))
+
+    if not args.no_extras:
+        # cost diagonal rebuild time and 10^6-shot sampling on the same handle
+        q.statevector(gamma, beta, copy=False)
+        torch.cuda.synchronize()
+        zt = torch.empty(w["shots"], dtype=torch.int64, device="cuda")
+        ct = torch.empty(w["shots"], dtype=torch.float64, device="cuda")
+        q.sample(w["shots"], w["sample_seed"], z_out=zt, cost_out=ct)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        q.sample(w["shots"], w["sample_seed"], z_out=zt, cost_out=ct)
+        torch.cuda.synchronize()
+        extra["sample_1e6_ms"] = 1e3 * (time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        E_ev = q.evaluate(gamma, beta)
+        extra["evaluate_ms"] = 1e3 * (time.perf_counter() - t0)
+        extra["evaluate_E"] = E_ev
+    q.close()
+    del q
+    torch.cuda.empty_cache()
+
+    if not args.no_extras and args.precision == "c128":
+        q64 = QaoaHandle.from_instance(inst, "c64")
+        dt64, prof64 = time_gradients(q64, gamma, beta, args.steps, 1)
+        E64, _, _ = q64.gradient(gamma, beta)
+        q64.close()
+        extra["c64"] = {"grad_evals_per_s": args.steps / dt64, "ms_per_step": 1e3 * dt64 / args.steps,
+                        "E": E64, "E_rel_diff_vs_c128": abs(E64 - E) / max(abs(E), 1.0),
+                        "passes": {k: {"launches": v[0], "ms": v[1], "bytes": v[2],
+                                       "gbs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
+                                   for k, v in prof64.items()}}
+        print(f"[bench] c64 {extra['c64']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print(f"[bench] cpu baseline: oracle at n={args.cpu_sample_n}", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(qi.workload_qubo32, args.cpu_sample_n, args.n, gamma, beta)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grad_evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "c128" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"QUBO n={args.n}, ER(0.1) couplings, J,h~N(0,1) seed 2, p={p}, "
+                         f"{'complex128' if s == 16 else 'complex64'} expectation + adjoint gradient"),
+            "n": args.n, "p": p, "terms": inst.m + args.n,
+            "state_bytes": int(N * s), "precision": args.precision,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -156,6 +156,21 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
 qaoa_status qaoa_sample(qaoa_handle h, int64_t shots, uint64_t seed, uint64_t *z, double *cost,
                         int32_t out_is_device);
 
+/*
+ * Kernel timing for measurement.  While enabled, every streaming pass launch
+ * (forward, turn and backward passes of qaoa_statevector / qaoa_evaluate /
+ * qaoa_gradient) is bracketed by a pair of HIP events on the handle's stream.
+ * qaoa_profile_enable (re)starts the counters (on != 0) or stops timing
+ * (on == 0).  qaoa_profile_read synchronises the stream and reports, for one
+ * pass kind (0 forward, 1 turn, 2 backward), the number of launches, their
+ * summed GPU time in milliseconds and their summed algorithmic bytes (each
+ * amplitude vector read or written once, plus one cost-diagonal read where the
+ * pass applies or measures C).  Any output pointer may be NULL.
+ */
+qaoa_status qaoa_profile_enable(qaoa_handle h, int32_t on);
+qaoa_status qaoa_profile_read(qaoa_handle h, int32_t kind, int64_t *launches, double *ms,
+                              double *bytes);
+
 /* Static English description of a status code. */
 const char *qaoa_status_string(qaoa_status s);
 

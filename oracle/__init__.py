@@ -62,6 +62,7 @@ def load() -> ctypes.CDLL:
         "oracle_philox4x32_10": (None, [vp, vp, vp]),
         "oracle_uniform53": (d, [u64, u64]),
         "oracle_sample": (i32, [i32, vp, vp, i64, u64, vp, vp]),
+        "oracle_num_threads": (i32, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -77,6 +78,11 @@ def _p(a: Optional[np.ndarray]):
 
 def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    """OpenMP threads used by the oracle's parallel loops."""
+    return int(load().oracle_num_threads())
 
 
 # ----------------------------------------------------------------- cost

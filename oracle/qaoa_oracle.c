@@ -33,6 +33,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -54,6 +55,9 @@ static void nsum_add(nsum *a, double x)
 static double nsum_value(const nsum *a) { return a->s + a->c; }
 
 #define ORACLE_CHUNKS 256
+
+/* Number of OpenMP threads the parallel loops below use. */
+int oracle_num_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ cost */
 

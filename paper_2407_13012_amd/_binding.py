@@ -54,6 +54,8 @@ def load_library() -> ctypes.CDLL:
         "qaoa_evaluate": [vp, i32, vp, vp, pd],
         "qaoa_gradient": [vp, i32, vp, vp, pd, vp, vp],
         "qaoa_sample": [vp, i64, u64, vp, vp, i32],
+        "qaoa_profile_enable": [vp, i32],
+        "qaoa_profile_read": [vp, i32, ctypes.POINTER(i64), pd, pd],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -222,6 +224,21 @@ def qaoa_sample(h, shots: int, seed: int, z_out=None, cost_out=None, with_cost: 
     return z, c
 
 
+PASS_KINDS = ("forward", "turn", "backward")
+
+
+def qaoa_profile_enable(h, on: bool = True) -> None:
+    _check(load_library().qaoa_profile_enable(h, 1 if on else 0), "qaoa_profile_enable")
+
+
+def qaoa_profile_read(h, kind: int):
+    """Return (launches, total_ms, total_algorithmic_bytes) for pass kind 0/1/2."""
+    n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(load_library().qaoa_profile_read(h, int(kind), ctypes.byref(n), ctypes.byref(ms),
+                                            ctypes.byref(by)), "qaoa_profile_read")
+    return n.value, ms.value, by.value
+
+
 def qaoa_status_string(status: int) -> str:
     return load_library().qaoa_status_string(status).decode()
 
@@ -297,3 +314,10 @@ class QaoaHandle:
 
     def sample(self, shots: int, seed: int, **kw):
         return qaoa_sample(self._h, shots, seed, **kw)
+
+    def profile_enable(self, on: bool = True):
+        qaoa_profile_enable(self._h, on)
+
+    def profile_read(self):
+        """{kind: (launches, ms, bytes)} for the forward, turn and backward passes."""
+        return {k: qaoa_profile_read(self._h, i) for i, k in enumerate(PASS_KINDS)}

@@ -51,6 +51,18 @@ struct qaoa_handle_s {
     bool poisoned = false;
     bool extrema_valid = false;
     double cmin = 0, cmax = 0;
+    // Kernel timing: event pairs bracketing pass launches, drained on read.
+    bool profiling = false;
+    struct Pending {
+        int kind;
+        double bytes;
+        hipEvent_t t0, t1;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    int64_t prof_launches[3] = {0, 0, 0};
+    double prof_ms[3] = {0, 0, 0};
+    double prof_bytes[3] = {0, 0, 0};
 };
 
 namespace {
@@ -184,9 +196,62 @@ qk::PassArgs pass_args(qaoa_handle h, const qk::Group &g)
     return a;
 }
 
+// Bytes a pass must move at minimum: each amplitude vector it reads and/or
+// writes once, plus one read of the cost diagonal when it applies or measures C.
+double pass_bytes(qaoa_handle h, int mode, const qk::PassArgs &a)
+{
+    const double N = (double)h->N, s = (double)amp_bytes(h->prec), c = (double)cost_bytes(h->prec);
+    const bool store = !(a.flags & qk::kNoStore);
+    const bool initd = (a.flags & qk::kInit) != 0;
+    if (mode == qk::kFwd)
+        return N * ((initd ? 0 : s) + (store ? s : 0) +
+                    ((a.flags & (qk::kPhaseIn | qk::kEOut)) ? c : 0));
+    if (mode == qk::kTurn) return N * ((initd ? 0 : s) + c + (store ? s : 0));
+    return N * (2 * s + (store ? 2 * s : 0) + ((a.flags & qk::kPhaseOut) ? c : 0));
+}
+
+qaoa_status take_event(qaoa_handle h, hipEvent_t *ev)
+{
+    if (!h->event_pool.empty()) {
+        *ev = h->event_pool.back();
+        h->event_pool.pop_back();
+        return QAOA_OK;
+    }
+    HIPCHECK(h, hipEventCreate(ev));
+    return QAOA_OK;
+}
+
 qaoa_status run_pass(qaoa_handle h, int mode, const qk::PassArgs &a)
 {
+    if (!h->profiling) {
+        HIPCHECK(h, qk::launch_pass(mode, c64(h), a, nblocks(h->n), h->stream));
+        return QAOA_OK;
+    }
+    qaoa_handle_s::Pending pd{mode, pass_bytes(h, mode, a), nullptr, nullptr};
+    qaoa_status st = take_event(h, &pd.t0);
+    if (st == QAOA_OK) st = take_event(h, &pd.t1);
+    if (st != QAOA_OK) return st;
+    HIPCHECK(h, hipEventRecord(pd.t0, h->stream));
     HIPCHECK(h, qk::launch_pass(mode, c64(h), a, nblocks(h->n), h->stream));
+    HIPCHECK(h, hipEventRecord(pd.t1, h->stream));
+    h->pending.push_back(pd);
+    return QAOA_OK;
+}
+
+qaoa_status drain_profile(qaoa_handle h)
+{
+    if (h->pending.empty()) return QAOA_OK;
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    for (auto &pd : h->pending) {
+        float ms = 0.f;
+        HIPCHECK(h, hipEventElapsedTime(&ms, pd.t0, pd.t1));
+        h->prof_launches[pd.kind] += 1;
+        h->prof_ms[pd.kind] += ms;
+        h->prof_bytes[pd.kind] += pd.bytes;
+        h->event_pool.push_back(pd.t0);
+        h->event_pool.push_back(pd.t1);
+    }
+    h->pending.clear();
     return QAOA_OK;
 }
 
@@ -378,6 +443,11 @@ qaoa_status qaoa_destroy(qaoa_handle h)
     if (h->cost) (void)hipFree(h->cost);
     if (h->parts) (void)hipFree(h->parts);
     if (h->res) (void)hipFree(h->res);
+    for (auto &pd : h->pending) {
+        (void)hipEventDestroy(pd.t0);
+        (void)hipEventDestroy(pd.t1);
+    }
+    for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
     return QAOA_OK;
@@ -622,6 +692,35 @@ qaoa_status qaoa_sample(qaoa_handle h, int64_t shots, uint64_t seed, uint64_t *z
             HIPCHECK(h, hipMemcpyAsync(cost, dc, (size_t)shots * 8, hipMemcpyDeviceToHost, h->stream));
         HIPCHECK(h, hipStreamSynchronize(h->stream));
     }
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_profile_enable(qaoa_handle h, int32_t on)
+{
+    qaoa_status st = check_handle(h);
+    if (st != QAOA_OK) return st;
+    DeviceGuard dg(h->device);
+    if ((st = drain_profile(h)) != QAOA_OK) return st;
+    h->profiling = on != 0;
+    for (int k = 0; k < 3; ++k) {
+        h->prof_launches[k] = 0;
+        h->prof_ms[k] = 0;
+        h->prof_bytes[k] = 0;
+    }
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_profile_read(qaoa_handle h, int32_t kind, int64_t *launches, double *ms,
+                              double *bytes)
+{
+    qaoa_status st = check_handle(h);
+    if (st != QAOA_OK) return st;
+    if (kind < 0 || kind > 2) return fail(QAOA_ERR_INVALID_ARGUMENT, "kind must be 0, 1 or 2");
+    DeviceGuard dg(h->device);
+    if ((st = drain_profile(h)) != QAOA_OK) return st;
+    if (launches) *launches = h->prof_launches[kind];
+    if (ms) *ms = h->prof_ms[kind];
+    if (bytes) *bytes = h->prof_bytes[kind];
     return QAOA_OK;
 }
 
