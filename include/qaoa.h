@@ -171,6 +171,21 @@ qaoa_status qaoa_profile_enable(qaoa_handle h, int32_t on);
 qaoa_status qaoa_profile_read(qaoa_handle h, int32_t kind, int64_t *launches, double *ms,
                               double *bytes);
 
+/*
+ * Pass plan of one mixer layer (host-side introspection; no GPU is touched).
+ * The n rotations exp(-i b X_j) of a layer commute (Eq. (1)), so the library
+ * applies them in a few sweeps over the state.  In sweep i one workgroup owns
+ * the 2^min(n,12) amplitudes whose indices differ only in the bits of
+ * tile_bits[i] and rotates the qubits in target_bits[i]; the remaining tile
+ * bits are low spectator bits kept for contiguous memory access.
+ *   cap       capacity of the two output arrays
+ *   npasses   receives the number of sweeps per layer
+ * Errors: INVALID_ARGUMENT for n outside [1, QAOA_MAX_QUBITS], an unknown
+ * precision, NULL outputs, or cap smaller than the number of sweeps.
+ */
+qaoa_status qaoa_pass_plan(int32_t n, int32_t precision, int32_t cap, int32_t *npasses,
+                           uint64_t *tile_bits, uint64_t *target_bits);
+
 /* Static English description of a status code. */
 const char *qaoa_status_string(qaoa_status s);
 

@@ -25,6 +25,7 @@ from ._binding import (  # noqa: F401
     qaoa_get_info,
     qaoa_gradient,
     qaoa_last_error_message,
+    qaoa_pass_plan,
     qaoa_profile_enable,
     qaoa_profile_read,
     qaoa_sample,

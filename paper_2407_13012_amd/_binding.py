@@ -54,6 +54,7 @@ def load_library() -> ctypes.CDLL:
         "qaoa_evaluate": [vp, i32, vp, vp, pd],
         "qaoa_gradient": [vp, i32, vp, vp, pd, vp, vp],
         "qaoa_sample": [vp, i64, u64, vp, vp, i32],
+        "qaoa_pass_plan": [i32, i32, i32, pi32, vp, vp],
         "qaoa_profile_enable": [vp, i32],
         "qaoa_profile_read": [vp, i32, ctypes.POINTER(i64), pd, pd],
     }
@@ -222,6 +223,16 @@ def qaoa_sample(h, shots: int, seed: int, z_out=None, cost_out=None, with_cost: 
     c = (np.zeros(m, dtype=np.float64) if with_cost else None) if cost_out is None else cost_out
     _check(lib.qaoa_sample(h, int(shots), int(seed) & (2**64 - 1), _ptr(z), _ptr(c), 0), "qaoa_sample")
     return z, c
+
+
+def qaoa_pass_plan(n: int, precision="c128"):
+    """[(tile_bits, target_bits)] of the sweeps that make up one mixer layer."""
+    cnt = ctypes.c_int32()
+    tb = np.zeros(16, dtype=np.uint64)
+    tg = np.zeros(16, dtype=np.uint64)
+    _check(load_library().qaoa_pass_plan(int(n), _PREC[precision], 16, ctypes.byref(cnt), _ptr(tb), _ptr(tg)),
+           "qaoa_pass_plan")
+    return [(int(tb[i]), int(tg[i])) for i in range(cnt.value)]
 
 
 PASS_KINDS = ("forward", "turn", "backward")

@@ -158,41 +158,47 @@ qaoa_status ensure_doubles(qaoa_handle h, double **buf, size_t *cap, size_t coun
     return QAOA_OK;
 }
 
-// Mixer groups of a layer: the low group covers bits [0, 12) (or all n < 12
-// bits); the remaining n-12 qubits are split into nearly equal high groups of
-// at most 10, each tile keeping 12-k low bits as contiguous spectators.
-std::vector<qk::Group> make_groups(int n)
-{
-    std::vector<qk::Group> g;
-    if (n <= qk::kTileBits) {
-        g.push_back({0, 0, n});
-        return g;
-    }
-    g.push_back({0, 0, qk::kTileBits});
-    const int r = n - qk::kTileBits, P = (r + 9) / 10;
-    int h = qk::kTileBits;
-    for (int i = 0; i < P; ++i) {
-        const int k = r / P + (i < r % P ? 1 : 0);
-        g.push_back({qk::kTileBits - k, h, k});
-        h += k;
-    }
-    return g;
-}
-
-qk::PassArgs pass_args(qaoa_handle h, const qk::Group &g)
+// Kernel arguments of one pass over plan entry `pp` with mixer angle `beta`.
+qk::PassArgs pass_args(qaoa_handle h, const qk::PassPlan &pp, double beta)
 {
     qk::PassArgs a;
     std::memset(&a, 0, sizeof a);
     a.psi = h->psi;
     a.lam = h->lam;
     a.cost = h->cost;
-    a.S = (uint32_t)g.S;
-    a.h = (uint32_t)g.h;
-    a.ta_bits = (uint32_t)(g.h - g.S);
-    a.tb_shift = (uint32_t)(g.h + g.k);
-    a.tbits = (uint32_t)(h->n < qk::kTileBits ? h->n : qk::kTileBits);
-    a.xcd_remap = (nblocks(h->n) % 32 == 0) ? 1u : 0u;
+    qk::make_geometry(h->n, pp, &a.geo);  // plans are validated when made
+    // Nontemporal accesses pay off for runs of >= 64 consecutive amplitudes; for
+    // short runs the L2 must keep each line for the neighbouring tile.
+    if (a.geo.t_dst[0] == 0 && a.geo.t_len[0] >= 6) a.flags |= qk::kStream;
+    // Send 16 consecutive tiles (adjacent runs, shared lines and DRAM rows) to one XCD.
+    const uint64_t T = nblocks(h->n);
+    for (uint32_t g = 4; g >= 1; --g)
+        if (T % (8ull << g) == 0) {
+            a.xcd_g = g;
+            break;
+        }
     a.amp0 = 1.0 / std::sqrt((double)h->N);
+    // Factored rotations: exp(-i b X) = f (p I - i q X) with the larger of
+    // |cos b|, |sin b| as f, so the non-unit coefficient has magnitude <= 1.
+    const double c = std::cos(beta), s = std::sin(beta);
+    const int k = __builtin_popcount(a.geo.tmask);
+    a.tan_mode = std::fabs(c) >= std::fabs(s) ? 1u : 0u;
+    if (a.tan_mode) {
+        a.mul_f = s / c;
+        a.mul_b = -s / c;
+        a.fac_f = c;
+        a.fac_b = c;
+    } else {
+        a.mul_f = c / s;
+        a.mul_b = -c / s;
+        a.fac_f = s;
+        a.fac_b = -s;
+    }
+    a.scl_f = a.scl_b = 1.0;
+    for (int i = 0; i < k; ++i) {
+        a.scl_f *= a.fac_f;
+        a.scl_b *= a.fac_b;
+    }
     return a;
 }
 
@@ -261,14 +267,12 @@ qaoa_status drain_profile(qaoa_handle h)
 qaoa_status run_forward(qaoa_handle h, int p, const double *gamma, const double *beta,
                         bool skip_last, bool e_out)
 {
-    const std::vector<qk::Group> G = make_groups(h->n);
+    const std::vector<qk::PassPlan> G = qk::plan_passes(h->n, c64(h));
     const int P = (int)G.size();
     for (int l = 0; l < p; ++l) {
         const int gend = (l == p - 1 && skip_last) ? P - 1 : P;
         for (int gi = 0; gi < gend; ++gi) {
-            qk::PassArgs a = pass_args(h, G[gi]);
-            a.cm = std::cos(beta[l]);
-            a.sm = std::sin(beta[l]);
+            qk::PassArgs a = pass_args(h, G[gi], beta[l]);
             if (gi == 0) {
                 a.flags |= qk::kPhaseIn;
                 a.gamma_in = gamma[l];
@@ -597,7 +601,7 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
     if ((st = ensure_doubles(h, &h->res, &h->res_cap, (size_t)nslots)) != QAOA_OK) return st;
     h->state_valid = false;
 
-    const std::vector<qk::Group> G = make_groups(h->n);
+    const std::vector<qk::PassPlan> G = qk::plan_passes(h->n, c64(h));
     const int P = (int)G.size();
     double *slotE = h->parts;
     auto slotB = [&](int l) { return h->parts + (uint64_t)(1 + l) * T; };
@@ -609,11 +613,7 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
     // Turn pass: last group of layer p-1 forward, E, lam = C phi, group undone on lam.
     {
         const int l = p - 1;
-        qk::PassArgs a = pass_args(h, G[P - 1]);
-        a.cm = std::cos(beta[l]);
-        a.sm = std::sin(beta[l]);
-        a.cu = a.cm;
-        a.su = -a.sm;
+        qk::PassArgs a = pass_args(h, G[P - 1], beta[l]);
         a.part_e = slotE;
         a.part_b = slotB(l);
         if (P == 1) {
@@ -628,9 +628,7 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
     for (int l = p - 1; l >= 0; --l) {
         const int gstart = (l == p - 1) ? P - 2 : P - 1;
         for (int gi = gstart; gi >= 0; --gi) {
-            qk::PassArgs a = pass_args(h, G[gi]);
-            a.cu = std::cos(beta[l]);
-            a.su = -std::sin(beta[l]);
+            qk::PassArgs a = pass_args(h, G[gi], beta[l]);
             a.part_b = slotB(l);
             // The first pass of a layer's sweep writes the beta partial (the turn
             // pass does so for layer p-1); later passes add to it.
@@ -721,6 +719,24 @@ qaoa_status qaoa_profile_read(qaoa_handle h, int32_t kind, int64_t *launches, do
     if (launches) *launches = h->prof_launches[kind];
     if (ms) *ms = h->prof_ms[kind];
     if (bytes) *bytes = h->prof_bytes[kind];
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_pass_plan(int32_t n, int32_t precision, int32_t cap, int32_t *npasses,
+                           uint64_t *tile_bits, uint64_t *target_bits)
+{
+    if (n < 1 || n > QAOA_MAX_QUBITS)
+        return fail(QAOA_ERR_INVALID_ARGUMENT, "n must be in [1, QAOA_MAX_QUBITS]");
+    if (precision != QAOA_C128 && precision != QAOA_C64)
+        return fail(QAOA_ERR_INVALID_ARGUMENT, "unknown precision");
+    if (!npasses || !tile_bits || !target_bits) return fail(QAOA_ERR_INVALID_ARGUMENT, "output is NULL");
+    const std::vector<qk::PassPlan> pl = qk::plan_passes(n, precision == QAOA_C64);
+    if ((int32_t)pl.size() > cap) return fail(QAOA_ERR_INVALID_ARGUMENT, "cap is too small");
+    *npasses = (int32_t)pl.size();
+    for (size_t i = 0; i < pl.size(); ++i) {
+        tile_bits[i] = pl[i].tile_bits;
+        target_bits[i] = pl[i].target_bits;
+    }
     return QAOA_OK;
 }
 

@@ -55,17 +55,52 @@ struct Tr<float> {
     using CT = float;
 };
 
+// Streaming accesses: with long contiguous runs every line is used once per
+// pass, so loads and stores may carry the nontemporal hint.  (The builtins take
+// clang vector types; values are kept in HIP vector types, which the compiler
+// register-allocates far more tightly.)
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ldnt(const double2 *p)
+{
+    const d2v t = __builtin_nontemporal_load((const d2v *)p);
+    return make_double2(t.x, t.y);
+}
+__device__ __forceinline__ float2 ldnt(const float2 *p)
+{
+    const f2v t = __builtin_nontemporal_load((const f2v *)p);
+    return make_float2(t.x, t.y);
+}
+__device__ __forceinline__ double ldnt(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ldnt(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void stnt(double2 v, double2 *p)
+{
+    d2v t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, (d2v *)p);
+}
+__device__ __forceinline__ void stnt(float2 v, float2 *p)
+{
+    f2v t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, (f2v *)p);
+}
+
 // ------------------------------------------------------------ tile geometry
 
 // XOR swizzle of the LDS slot: conflict-free 16 B accesses in all three arrangements.
 __device__ __forceinline__ uint32_t lds_slot(uint32_t e) { return e ^ ((e >> 4) & 15u); }
 
 template <int ARR>
-__device__ __forceinline__ uint32_t elem(uint32_t lane, uint32_t wave, uint32_t r)
+__host__ __device__ __forceinline__ constexpr uint32_t elem(uint32_t lane, uint32_t wave,
+                                                            uint32_t r)
 {
-    if constexpr (ARR == 0) return lane | (r << 6) | (wave << 10);
-    else if constexpr (ARR == 1) return r | (lane << 4) | (wave << 10);
-    else return (lane & 15u) | ((r & 3u) << 4) | ((lane >> 4) << 6) | (wave << 8) | ((r >> 2) << 10);
+    return ARR == 0   ? (lane | (r << 6) | (wave << 10))
+           : ARR == 1 ? (r | (lane << 4) | (wave << 10))
+                      : ((lane & 15u) | ((r & 3u) << 4) | ((lane >> 4) << 6) | (wave << 8) |
+                         ((r >> 2) << 10));
 }
 
 // Tile bit held by register-index bit q in arrangement ARR.
@@ -75,10 +110,24 @@ __host__ __device__ constexpr uint32_t regbit(int q)
     return ARR == 0 ? 6 + q : (ARR == 1 ? q : (q < 2 ? 4 + q : 8 + q));
 }
 
-// Tile-local index -> offset from the tile base: bits [0,S) stay, bits >= S move to h.
-__device__ __forceinline__ uint64_t dep(uint32_t e, uint32_t S, uint32_t h)
+// Tile-local index -> offset of the amplitude from the tile base.
+__device__ __forceinline__ uint64_t dep(uint32_t e, const Geometry &g)
 {
-    return (uint64_t)(e & ((1u << S) - 1u)) | ((uint64_t)(e >> S) << h);
+    uint64_t o = 0;
+#pragma unroll
+    for (int r = 0; r < kTileRuns; ++r)
+        o |= (uint64_t)((e >> g.t_src[r]) & ((1u << g.t_len[r]) - 1u)) << g.t_dst[r];
+    return o;
+}
+
+// Tile index -> base index of the tile (the tile bits set to zero).
+__device__ __forceinline__ uint64_t tile_base(uint64_t t, const Geometry &g)
+{
+    uint64_t o = 0;
+#pragma unroll
+    for (int r = 0; r < kFreeRuns; ++r)
+        o |= ((t >> g.f_src[r]) & ((1ull << g.f_len[r]) - 1ull)) << g.f_dst[r];
+    return o;
 }
 
 // ------------------------------------------------------------ arithmetic
@@ -89,6 +138,15 @@ __device__ __forceinline__ V cmul(V v, R c, R s)
     V o;
     o.x = v.x * c - v.y * s;
     o.y = v.x * s + v.y * c;
+    return o;
+}
+
+template <typename V, typename R>
+__device__ __forceinline__ V vscale(V v, R f)
+{
+    V o;
+    o.x = v.x * f;
+    o.y = v.y * f;
     return o;
 }
 
@@ -105,11 +163,52 @@ __device__ __forceinline__ double imcx(V u, V v)
     return (double)u.x * (double)v.y - (double)u.y * (double)v.x;
 }
 
-// cos / sin of g * C.  complex128: fp64 sincos.  complex64: the product is formed
-// and reduced modulo 2 pi in fp64, then an fp32 sincos is taken.
+// sin and cos of x in fp64.  Cody-Waite reduction x = k pi/2 + r with pi/2
+// split into two 33-bit parts and a remainder (k pi/2 is exact for |k| < 2^20),
+// then the Taylor series of sin (to r^17) and cos (to r^18) on |r| <= pi/4,
+// whose truncation error is below 1e-19.  Larger arguments use the library.
+__device__ __forceinline__ void sincos_cw(double x, double &s, double &c)
+{
+    if (!(fabs(x) < 1.0e6)) {
+        sincos(x, &s, &c);
+        return;
+    }
+    const double k = rint(x * 0x1.45f306dc9c883p-1);  // 2/pi
+    double r = fma(-k, 0x1.921fb54400000p+0, x);
+    r = fma(-k, 0x1.0b4611a600000p-34, r);
+    r = fma(-k, 0x1.3198a2e037073p-69, r);
+    const double r2 = r * r;
+    double ps = 2.8114572543455206e-15;  //  1/17!
+    ps = fma(ps, r2, -7.647163731819816e-13);   // -1/15!
+    ps = fma(ps, r2, 1.6059043836821613e-10);   //  1/13!
+    ps = fma(ps, r2, -2.505210838544172e-08);   // -1/11!
+    ps = fma(ps, r2, 2.7557319223985893e-06);   //  1/9!
+    ps = fma(ps, r2, -0.0001984126984126984);   // -1/7!
+    ps = fma(ps, r2, 0.008333333333333333);     //  1/5!
+    ps = fma(ps, r2, -0.16666666666666666);     // -1/3!
+    const double sr = fma(ps * r2, r, r);
+    double pc = -1.5619206968586225e-16;  // -1/18!
+    pc = fma(pc, r2, 4.779477332387385e-14);    //  1/16!
+    pc = fma(pc, r2, -1.1470745597729725e-11);  // -1/14!
+    pc = fma(pc, r2, 2.08767569878681e-09);     //  1/12!
+    pc = fma(pc, r2, -2.755731922398589e-07);   // -1/10!
+    pc = fma(pc, r2, 2.48015873015873e-05);     //  1/8!
+    pc = fma(pc, r2, -0.001388888888888889);    // -1/6!
+    pc = fma(pc, r2, 0.041666666666666664);     //  1/4!
+    pc = fma(pc, r2, -0.5);                     // -1/2!
+    const double cr = fma(pc, r2, 1.0);
+    const int q = (int)(((long long)k) & 3);
+    // x = k pi/2 + r: rotate (cos r, sin r) by q quarter turns
+    const double s0 = (q & 1) ? cr : sr, c0 = (q & 1) ? sr : cr;
+    s = (q & 2) ? -s0 : s0;
+    c = ((q + 1) & 2) ? -c0 : c0;
+}
+
+// cos / sin of g * C.  complex128: fp64.  complex64: the product is formed and
+// reduced modulo 2 pi in fp64, then an fp32 sincos is taken.
 __device__ __forceinline__ void phase_cs(double g, double cval, double &c, double &s)
 {
-    sincos(g * cval, &s, &c);
+    sincos_cw(g * cval, s, c);
 }
 __device__ __forceinline__ void phase_cs(double g, float cval, float &c, float &s)
 {
@@ -120,52 +219,64 @@ __device__ __forceinline__ void phase_cs(double g, float cval, float &c, float &
     sincosf((float)r, &s, &c);
 }
 
-// (a, b) <- (c a - i s b, -i s a + c b): exp(-i beta X) with c = cos beta, s = sin beta.
-template <typename V, typename R>
-__device__ __forceinline__ void bfly(V &a, V &b, R c, R s)
+// Factored rotation exp(-i b X) / f on the pair (a, b'):
+//   tan mode (TM):  a <- a - i m b',     b' <- b' - i m a
+//   cot mode:       a <- m a - i b',     b' <- m b' - i a
+// (same formula for the inverse rotation with its own m); one FMA per component.
+template <bool TM, typename V, typename R>
+__device__ __forceinline__ void bfly(V &a, V &b, R m)
 {
     const R ax = a.x, ay = a.y, bx = b.x, by = b.y;
-    a.x = c * ax + s * by;
-    a.y = c * ay - s * bx;
-    b.x = c * bx + s * ay;
-    b.y = c * by - s * ax;
+    if constexpr (TM) {
+        a.x = fma(m, by, ax);
+        a.y = fma(-m, bx, ay);
+        b.x = fma(m, ay, bx);
+        b.y = fma(-m, ax, by);
+    } else {
+        a.x = fma(m, ax, by);
+        a.y = fma(m, ay, -bx);
+        b.x = fma(m, bx, ay);
+        b.y = fma(m, by, -ax);
+    }
 }
 
-template <int ARR, typename V, typename R>
-__device__ __forceinline__ void mix_stage(V (&v)[16], R c, R s, uint32_t S, uint32_t tbits)
+template <int ARR, bool TM, typename V, typename R>
+__device__ __forceinline__ void mix_stage(V (&v)[16], R m, uint32_t tmask)
 {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const uint32_t lb = regbit<ARR>(q);
-        if (lb >= S && lb < tbits) {
+        if ((tmask >> regbit<ARR>(q)) & 1u) {
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                if (!(r & (1 << q))) bfly(v[r], v[r | (1 << q)], c, s);
+                if (!(r & (1 << q))) bfly<TM>(v[r], v[r | (1 << q)], m);
         }
     }
 }
 
 // Adjoint stage: for each target bit, add Im<lam|X_j|phi> over the register
-// pairs, then apply the (inverse) rotation to both vectors.
-template <int ARR, typename V, typename R>
-__device__ __forceinline__ void adj_stage(V (&f)[16], V (&l)[16], R c, R s, uint32_t S,
-                                          uint32_t tbits, double &accB)
+// pairs (weighted by sig2, the squared factor both vectors still miss), then
+// apply the factored inverse rotation to both.
+template <int ARR, bool TM, typename V, typename R>
+__device__ __forceinline__ void adj_stage(V (&f)[16], V (&l)[16], R m, uint32_t tmask,
+                                          double &sig2, double f2, double &accB)
 {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const uint32_t lb = regbit<ARR>(q);
-        if (lb >= S && lb < tbits) {
+        if ((tmask >> regbit<ARR>(q)) & 1u) {
+            double ps = 0.0;
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 if (!(r & (1 << q))) {
                     const int r1 = r | (1 << q);
-                    accB += imcx(l[r], f[r1]) + imcx(l[r1], f[r]);
+                    ps += imcx(l[r], f[r1]) + imcx(l[r1], f[r]);
                 }
+            accB = fma(sig2, ps, accB);
+            sig2 *= f2;
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 if (!(r & (1 << q))) {
-                    bfly(l[r], l[r | (1 << q)], c, s);
-                    bfly(f[r], f[r | (1 << q)], c, s);
+                    bfly<TM>(l[r], l[r | (1 << q)], m);
+                    bfly<TM>(f[r], f[r | (1 << q)], m);
                 }
         }
     }
@@ -203,9 +314,21 @@ __device__ __forceinline__ double block_sum(double x, double *scratch)
     return r;
 }
 
+template <typename T>
+__device__ __forceinline__ T ld(const T *p, bool stream)
+{
+    return stream ? ldnt(p) : *p;
+}
+template <typename T>
+__device__ __forceinline__ void st(T v, T *p, bool stream)
+{
+    if (stream) stnt(v, p);
+    else *p = v;
+}
+
 // ------------------------------------------------------------ pass kernel
 
-template <typename R, int MODE>
+template <typename R, int MODE, bool TM>
 __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
 {
     using V = typename Tr<R>::V;
@@ -214,19 +337,26 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
 
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     const uint64_t b = blockIdx.x;
-    const uint64_t t = a.xcd_remap ? ((b & ~31ull) | ((b & 7ull) << 2) | ((b >> 3) & 3ull)) : b;
-    const uint64_t base =
-        ((t & ((1ull << a.ta_bits) - 1ull)) << a.S) | ((t >> a.ta_bits) << a.tb_shift);
-    const bool full = a.tbits == (uint32_t)kTileBits;
-    const uint32_t lim = 1u << a.tbits;
+    // 2^G consecutive tiles per XCD: workgroups are dealt to the 8 XCDs in turn
+    const uint32_t G = a.xcd_g;
+    const uint64_t t = G ? ((b & ~((8ull << G) - 1ull)) | ((b & 7ull) << G) | ((b >> 3) & ((1ull << G) - 1ull)))
+                         : b;
+    const Geometry &g = a.geo;
+    const uint64_t base = tile_base(t, g);
+    const bool full = g.tbits == (uint32_t)kTileBits;
+    const uint32_t lim = 1u << g.tbits;
+    const uint32_t tmask = g.tmask;
+    const bool strm = (a.flags & kStream) != 0;
     V *psi = (V *)a.psi;
     V *lam = (V *)a.lam;
     const CT *cost = (const CT *)a.cost;
 
-    const uint64_t thrA = base | dep(elem<0>(lane, wave, 0), a.S, a.h);
-    const uint64_t thrC = base | dep(elem<2>(lane, wave, 0), a.S, a.h);
-#define ZA(r) (thrA | dep(elem<0>(0, 0, (r)), a.S, a.h))
-#define ZC(r) (thrC | dep(elem<2>(0, 0, (r)), a.S, a.h))
+    // Global index of register r in arrangement A / C: a per-thread part plus a
+    // part that depends on r only (the same for every thread of the grid).
+    const uint64_t thrA = base | dep(elem<0>(lane, wave, 0), g);
+    const uint64_t thrC = base | dep(elem<2>(lane, wave, 0), g);
+#define ZA(r) (thrA | dep(elem<0>(0, 0, (r)), g))
+#define ZC(r) (thrC | dep(elem<2>(0, 0, (r)), g))
 #define VA(r) (full || elem<0>(lane, wave, (r)) < lim)
 #define VC(r) (full || elem<2>(lane, wave, (r)) < lim)
 
@@ -241,68 +371,79 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
             for (int r = 0; r < 16; ++r) v[r] = VA(r) ? a0 : zero;
         } else {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = VA(r) ? psi[ZA(r)] : zero;
+            for (int r = 0; r < 16; ++r) v[r] = VA(r) ? ld(&psi[ZA(r)], strm) : zero;
         }
         if (a.flags & kPhaseIn) {
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 if (VA(r)) {
                     R c, s;
-                    phase_cs(-a.gamma_in, cost[ZA(r)], c, s);
+                    phase_cs(-a.gamma_in, ld(&cost[ZA(r)], strm), c, s);
                     v[r] = cmul(v[r], c, s);
                 }
         }
-        const R cm = (R)a.cm, sm = (R)a.sm;
-        mix_stage<0>(v, cm, sm, a.S, a.tbits);
+        const R mf = (R)a.mul_f;
+        mix_stage<0, TM>(v, mf, tmask);
         xpose<0, 1>(v, lds, lane, wave);
-        mix_stage<1>(v, cm, sm, a.S, a.tbits);
+        mix_stage<1, TM>(v, mf, tmask);
         xpose<1, 2>(v, lds, lane, wave);
-        mix_stage<2>(v, cm, sm, a.S, a.tbits);
+        mix_stage<2, TM>(v, mf, tmask);
+        const R sf = (R)a.scl_f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = vscale(v[r], sf);
 
         if constexpr (MODE == kFwd) {
             if (a.flags & kEOut) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
-                    if (VC(r)) accE += (double)cost[ZC(r)] * norm2(v[r]);
+                    if (VC(r)) accE += (double)ld(&cost[ZC(r)], strm) * norm2(v[r]);
             }
             if (!(a.flags & kNoStore)) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
-                    if (VC(r)) psi[ZC(r)] = v[r];
+                    if (VC(r)) st(v[r], &psi[ZC(r)], strm);
             }
         } else {
-            // v is the final state phi on this tile: E, lam = C phi, then undo the group.
+            // v is the final state phi on this tile: E, lam = C phi, then undo the
+            // group on both, visiting the register arrangements C, B, A, and
+            // return lam to arrangement C (where C is already loaded) to store it.
             V l[16];
+            CT cv[16];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const CT cv = VC(r) ? cost[ZC(r)] : (CT)0;
-                accE += (double)cv * norm2(v[r]);
-                l[r].x = (R)cv * v[r].x;
-                l[r].y = (R)cv * v[r].y;
+                cv[r] = VC(r) ? ld(&cost[ZC(r)], strm) : (CT)0;
+                accE += (double)cv[r] * norm2(v[r]);
+                l[r] = vscale(v[r], (R)cv[r]);
             }
-            const R cu = (R)a.cu, su = (R)a.su;
-            adj_stage<2>(v, l, cu, su, a.S, a.tbits, accB);
+            const R mb = (R)a.mul_b;
+            const double f2 = a.fac_b * a.fac_b;
+            double sig2 = 1.0;
+            adj_stage<2, TM>(v, l, mb, tmask, sig2, f2, accB);
             xpose<2, 1>(v, lds, lane, wave);
             xpose<2, 1>(l, lds, lane, wave);
-            adj_stage<1>(v, l, cu, su, a.S, a.tbits, accB);
+            adj_stage<1, TM>(v, l, mb, tmask, sig2, f2, accB);
             xpose<1, 0>(v, lds, lane, wave);
             xpose<1, 0>(l, lds, lane, wave);
-            adj_stage<0>(v, l, cu, su, a.S, a.tbits, accB);
+            adj_stage<0, TM>(v, l, mb, tmask, sig2, f2, accB);
+            const R sb = (R)a.scl_b;
+            xpose<0, 2>(l, lds, lane, wave);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) l[r] = vscale(l[r], sb);
             if (a.flags & kPhaseOut) {
+                xpose<0, 2>(v, lds, lane, wave);
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
-                    if (VA(r)) {
-                        const CT cv = cost[ZA(r)];
-                        accG += (double)cv * imcx(l[r], v[r]);
+                    if (VC(r)) {
+                        accG += (double)cv[r] * imcx(l[r], vscale(v[r], sb));
                         R c, s;
-                        phase_cs(a.gamma_out, cv, c, s);
+                        phase_cs(a.gamma_out, cv[r], c, s);
                         l[r] = cmul(l[r], c, s);
                     }
             }
             if (!(a.flags & kNoStore)) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
-                    if (VA(r)) lam[ZA(r)] = l[r];
+                    if (VC(r)) st(l[r], &lam[ZC(r)], strm);
             }
         }
     } else {
@@ -310,22 +451,30 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const bool ok = VA(r);
-            f[r] = ok ? psi[ZA(r)] : zero;
-            l[r] = ok ? lam[ZA(r)] : zero;
+            f[r] = ok ? ld(&psi[ZA(r)], strm) : zero;
+            l[r] = ok ? ld(&lam[ZA(r)], strm) : zero;
         }
-        const R cu = (R)a.cu, su = (R)a.su;
-        adj_stage<0>(f, l, cu, su, a.S, a.tbits, accB);
+        const R mb = (R)a.mul_b;
+        const double f2 = a.fac_b * a.fac_b;
+        double sig2 = 1.0;
+        adj_stage<0, TM>(f, l, mb, tmask, sig2, f2, accB);
         xpose<0, 1>(f, lds, lane, wave);
         xpose<0, 1>(l, lds, lane, wave);
-        adj_stage<1>(f, l, cu, su, a.S, a.tbits, accB);
+        adj_stage<1, TM>(f, l, mb, tmask, sig2, f2, accB);
         xpose<1, 2>(f, lds, lane, wave);
         xpose<1, 2>(l, lds, lane, wave);
-        adj_stage<2>(f, l, cu, su, a.S, a.tbits, accB);
+        adj_stage<2, TM>(f, l, mb, tmask, sig2, f2, accB);
+        const R sb = (R)a.scl_b;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            f[r] = vscale(f[r], sb);
+            l[r] = vscale(l[r], sb);
+        }
         if (a.flags & kPhaseOut) {
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 if (VC(r)) {
-                    const CT cv = cost[ZC(r)];
+                    const CT cv = ld(&cost[ZC(r)], strm);
                     accG += (double)cv * imcx(l[r], f[r]);
                     R c, s;
                     phase_cs(a.gamma_out, cv, c, s);
@@ -337,8 +486,8 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 if (VC(r)) {
-                    psi[ZC(r)] = f[r];
-                    lam[ZC(r)] = l[r];
+                    st(f[r], &psi[ZC(r)], strm);
+                    st(l[r], &lam[ZC(r)], strm);
                 }
         }
     }
@@ -696,17 +845,23 @@ inline unsigned grid_for(uint64_t N, uint64_t cap = 1ull << 20)
 
 // ------------------------------------------------------------ launchers
 
+template <typename R, bool TM>
+static void launch_pass_t(int mode, const PassArgs &a, dim3 grid, hipStream_t s)
+{
+    if (mode == kFwd) hipLaunchKernelGGL((k_pass<R, kFwd, TM>), grid, dim3(kThreads), 0, s, a);
+    else if (mode == kTurn) hipLaunchKernelGGL((k_pass<R, kTurn, TM>), grid, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((k_pass<R, kBwd, TM>), grid, dim3(kThreads), 0, s, a);
+}
+
 hipError_t launch_pass(int mode, bool c64, const PassArgs &a, uint64_t nblocks, hipStream_t s)
 {
-    const dim3 grid((unsigned)nblocks), block(kThreads);
+    const dim3 grid((unsigned)nblocks);
     if (!c64) {
-        if (mode == kFwd) hipLaunchKernelGGL((k_pass<double, kFwd>), grid, block, 0, s, a);
-        else if (mode == kTurn) hipLaunchKernelGGL((k_pass<double, kTurn>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_pass<double, kBwd>), grid, block, 0, s, a);
+        if (a.tan_mode) launch_pass_t<double, true>(mode, a, grid, s);
+        else launch_pass_t<double, false>(mode, a, grid, s);
     } else {
-        if (mode == kFwd) hipLaunchKernelGGL((k_pass<float, kFwd>), grid, block, 0, s, a);
-        else if (mode == kTurn) hipLaunchKernelGGL((k_pass<float, kTurn>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_pass<float, kBwd>), grid, block, 0, s, a);
+        if (a.tan_mode) launch_pass_t<float, true>(mode, a, grid, s);
+        else launch_pass_t<float, false>(mode, a, grid, s);
     }
     return hipGetLastError();
 }
@@ -750,10 +905,10 @@ hipError_t launch_fill_plus(bool c64, void *psi, int n, hipStream_t s)
     const double amp = 1.0 / sqrt((double)N);
     if (c64)
         hipLaunchKernelGGL(k_fill_plus<float>, dim3(grid_for(N)), dim3(kThreads), 0, s,
-                           (float2 *)psi, N, (float)amp);
+                           (Tr<float>::V *)psi, N, (float)amp);
     else
         hipLaunchKernelGGL(k_fill_plus<double>, dim3(grid_for(N)), dim3(kThreads), 0, s,
-                           (double2 *)psi, N, amp);
+                           (Tr<double>::V *)psi, N, amp);
     return hipGetLastError();
 }
 
@@ -763,11 +918,11 @@ hipError_t launch_expect(bool c64, const void *psi, const void *C, int n, double
     const uint64_t N = 1ull << n;
     const unsigned nb = (unsigned)((N + kTile - 1) / kTile);
     if (c64)
-        hipLaunchKernelGGL(k_expect<float>, dim3(nb), dim3(kThreads), 0, s, (const float2 *)psi,
+        hipLaunchKernelGGL(k_expect<float>, dim3(nb), dim3(kThreads), 0, s, (const Tr<float>::V *)psi,
                            (const float *)C, N, parts);
     else
         hipLaunchKernelGGL(k_expect<double>, dim3(nb), dim3(kThreads), 0, s,
-                           (const double2 *)psi, (const double *)C, N, parts);
+                           (const Tr<double>::V *)psi, (const double *)C, N, parts);
     return hipGetLastError();
 }
 
@@ -815,11 +970,11 @@ hipError_t launch_submass(bool c64, const void *psi, int n, int sbits, double *s
     const uint64_t N = 1ull << n, nsub = 1ull << (n - sbits);
     const unsigned nb = (unsigned)((nsub + 3) / 4);
     if (c64)
-        hipLaunchKernelGGL(k_submass<float>, dim3(nb), dim3(kThreads), 0, s, (const float2 *)psi,
+        hipLaunchKernelGGL(k_submass<float>, dim3(nb), dim3(kThreads), 0, s, (const Tr<float>::V *)psi,
                            N, sbits, nsub, sub);
     else
         hipLaunchKernelGGL(k_submass<double>, dim3(nb), dim3(kThreads), 0, s,
-                           (const double2 *)psi, N, sbits, nsub, sub);
+                           (const Tr<double>::V *)psi, N, sbits, nsub, sub);
     return hipGetLastError();
 }
 
@@ -843,11 +998,11 @@ hipError_t launch_shots(bool c64, const void *psi, const void *C, int n, int sbi
     const uint64_t N = 1ull << n;
     const unsigned nb = (unsigned)(((uint64_t)shots + kThreads - 1) / kThreads);
     if (c64)
-        hipLaunchKernelGGL(k_shots<float>, dim3(nb), dim3(kThreads), 0, s, (const float2 *)psi,
+        hipLaunchKernelGGL(k_shots<float>, dim3(nb), dim3(kThreads), 0, s, (const Tr<float>::V *)psi,
                            (const float *)C, N, sbits, pre, nsub, shots, seed, z, cost);
     else
         hipLaunchKernelGGL(k_shots<double>, dim3(nb), dim3(kThreads), 0, s,
-                           (const double2 *)psi, (const double *)C, N, sbits, pre, nsub, shots,
+                           (const Tr<double>::V *)psi, (const double *)C, N, sbits, pre, nsub, shots,
                            seed, z, cost);
     return hipGetLastError();
 }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace qk {
 
 // Tile geometry of the streaming pass kernel: one workgroup owns 2^12
@@ -26,14 +28,37 @@ enum PassFlags : int {
     kEOut = 4,       // accumulate sum C |psi|^2 (kFwd after the mixer; always in kTurn)
     kPhaseOut = 8,   // (kBwd, kTurn) accumulate Im <lam|C|phi>, then multiply both by exp(+i gamma_out C)
     kNoStore = 16,   // skip the final store (last backward pass)
-    kBetaAcc = 32    // add the <lam|X|phi> partial to the existing one instead of overwriting
+    kBetaAcc = 32,   // add the <lam|X|phi> partial to the existing one instead of overwriting
+    kStream = 64     // nontemporal loads/stores (tiles with long contiguous runs)
 };
 
-// A mixer group: tile bits are [0, S) (spectators or targets) and [h, h+k);
-// S + k = 12 for n >= 12.  Targets are the tile bits >= S and < tbits.
-struct Group {
-    int S, h, k;
+// One pass of a mixer layer.  A tile is the set of 2^12 basis indices that
+// agree outside `tile_bits`; the pass rotates the qubits in `target_bits`
+// (a subset of tile_bits; the rest are spectators kept for contiguous access).
+struct PassPlan {
+    uint64_t tile_bits;
+    uint64_t target_bits;
 };
+
+constexpr int kTileRuns = 4;  // runs of consecutive global bits inside a tile
+constexpr int kFreeRuns = 5;  // runs of consecutive global bits of the tile index
+
+// Tile geometry in kernel form: tile-local bit (src + i) of run r sits at
+// global bit (dst + i), i < len; likewise for the tile-index bits.
+struct Geometry {
+    uint32_t t_src[kTileRuns], t_dst[kTileRuns], t_len[kTileRuns];
+    uint32_t f_src[kFreeRuns], f_dst[kFreeRuns], f_len[kFreeRuns];
+    uint32_t tmask;  // tile-local bits that are rotated
+    uint32_t tbits;  // number of valid tile-local bits (12, or n when n < 12)
+};
+
+// Pass plan of one mixer layer on n qubits (host).  Every qubit is a target of
+// exactly one pass; the first pass holds bits [0, 12 - x) plus x high bits.
+// Qubits whose stride crosses a 2 MiB page are spread evenly over the passes
+// so that no tile touches more than a few dozen pages.
+std::vector<PassPlan> plan_passes(int n, bool c64);
+// Kernel geometry of a plan entry; returns false if it needs more runs than supported.
+bool make_geometry(int n, const PassPlan &pp, Geometry *g);
 
 struct PassArgs {
     void *psi;          // state / phi (in-out)
@@ -42,13 +67,17 @@ struct PassArgs {
     double *part_e;     // per-block partial sums, indexed by blockIdx.x
     double *part_b;
     double *part_g;
-    uint32_t S, h;      // group geometry
-    uint32_t ta_bits;   // h - S: tile-index bits placed at [S, h)
-    uint32_t tb_shift;  // h + k: remaining tile-index bits placed from here
-    uint32_t tbits;     // number of valid tile bits (12, or n when n < 12)
-    uint32_t xcd_remap; // map consecutive tiles to one XCD (needs #tiles % 32 == 0)
-    double cm, sm;      // mixer: cos(beta), sin(beta) of exp(-i beta X) (kFwd, kTurn forward)
-    double cu, su;      // mixer^dag coefficients: cos(beta), -sin(beta) (kBwd, kTurn backward)
+    Geometry geo;
+    uint32_t xcd_g;     // 2^xcd_g consecutive tiles go to one XCD (0: hardware order)
+    // Mixer rotations in factored form.  exp(-i b X) = f (p I - i q X) with
+    // (f, p, q) = (cos b, 1, tan b) when |cos b| >= |sin b| ("tan" mode) and
+    // (sin b, cot b, 1) otherwise, so a rotation costs one FMA per component;
+    // the factor f^k of the k rotated qubits is applied once per pass.
+    uint32_t tan_mode;  // 1: p = 1, mul = q;  0: q = 1, mul = p
+    double mul_f;       // forward rotation exp(-i b X): the non-unit coefficient
+    double mul_b;       // inverse rotation exp(+i b X)
+    double fac_f, fac_b;  // per-rotation factor f (forward, inverse)
+    double scl_f, scl_b;  // f^k over the pass's k target qubits
     double gamma_in;    // kPhaseIn multiplies by exp(-i gamma_in C)
     double gamma_out;   // kPhaseOut multiplies by exp(+i gamma_out C)
     double amp0;        // 2^{-n/2}

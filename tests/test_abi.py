@@ -135,3 +135,50 @@ def test_python_binding_has_c_names():
     import paper_2407_13012_amd as pkg
     for f in declared_functions():
         assert hasattr(pkg, f), f
+
+
+# ---------------------------------------------------------------- pass planning (host logic)
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_pass_plan_invariants(prec):
+    from paper_2407_13012_amd import qaoa_pass_plan
+    page = 17 if prec == "c128" else 18
+    for n in range(1, 41):
+        plan = qaoa_pass_plan(n, prec)
+        seen = 0
+        for i, (tile, tgt) in enumerate(plan):
+            assert bin(tile).count("1") == min(n, 12)
+            assert tgt & ~tile == 0 and tgt & seen == 0
+            assert tile < (1 << n)
+            seen |= tgt
+            spect = tile & ~tgt
+            # spectators are the lowest bits, contiguous from bit 0
+            assert spect & (spect + 1) == 0
+            # the first pass starts with >= 6 consecutive low target bits (>= 64 amplitudes)
+            if i == 0:
+                assert tgt & 63 == min(63, (1 << n) - 1)
+            elif n > 12:
+                assert spect >= 3  # at least 2 spectator bits (>= 4 consecutive amplitudes)
+        assert seen == (1 << n) - 1
+        assert len(plan) == (1 if n <= 12 else 1 + -(-(n - 12) // 10))
+        # page-crossing qubits are spread evenly
+        X = max(0, n - page)
+        if X:
+            per = [bin(t >> page).count("1") for _, t in plan]
+            assert max(per) - min(per) <= 1, (n, per)
+
+
+def test_pass_plan_n32_geometry():
+    from paper_2407_13012_amd import qaoa_pass_plan
+    plan = qaoa_pass_plan(32, "c128")
+    assert len(plan) == 3
+    assert [bin(t >> 17).count("1") for _, t in plan] == [5, 5, 5]
+    assert plan[0][1] & 127 == 127          # 7 consecutive low qubits in the first pass
+
+
+def test_pass_plan_rejects():
+    from paper_2407_13012_amd import QaoaError, qaoa_pass_plan
+    with pytest.raises(QaoaError):
+        qaoa_pass_plan(0)
+    with pytest.raises(QaoaError):
+        qaoa_pass_plan(41)
