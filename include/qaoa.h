@@ -157,6 +157,47 @@ qaoa_status qaoa_sample(qaoa_handle h, int64_t shots, uint64_t seed, uint64_t *z
                         int32_t out_is_device);
 
 /*
+ * Limited-memory BFGS (Sec. V-C offers L-BFGS natively; Liu & Nocedal 1989):
+ * two-loop recursion with m stored correction pairs and a strong-Wolfe line
+ * search (c1 = 1e-4, c2 = 0.9).  Every trial point costs one evaluation.
+ */
+typedef int (*qaoa_objective_fn)(const double *x, double *f, double *g, void *user);
+/* f(x) and its gradient g(x); return 0 on success, nonzero to stop the optimiser. */
+
+typedef struct {
+    int32_t max_iter;  /* accepted steps, >= 0 */
+    int32_t history;   /* stored correction pairs m, >= 1 */
+    double gtol;       /* stop when max_i |g_i| <= gtol */
+    double ftol;       /* stop when |f_k - f_k+1| <= ftol * max(1, |f_k+1|); 0 disables */
+    int32_t max_evals; /* cap on evaluations, >= 1 */
+} qaoa_lbfgs_options;
+
+/*
+ * Minimise fn over R^dim starting from x (host, in-out).  opt NULL means
+ * {100, 10, 1e-8, 0, 1000}.  Outputs (each may be NULL): fx = f at the returned
+ * x, iters = accepted steps, evals = evaluations used, trace_x [(max_iter+1) x
+ * dim] and trace_f [max_iter+1] receive the iterates x_0 .. x_iters and their f.
+ * The search stops early (returning the best accepted point) when the line
+ * search fails or max_evals is reached.
+ * Errors: INVALID_ARGUMENT (dim < 1, NULL x/fn, bad options, non-finite x);
+ * DEVICE if the first evaluation fails.
+ */
+qaoa_status qaoa_lbfgs_minimize(int32_t dim, double *x, qaoa_objective_fn fn, void *user,
+                                const qaoa_lbfgs_options *opt, double *fx, int32_t *iters,
+                                int32_t *evals, double *trace_x, double *trace_f);
+
+/*
+ * Maximise E(gamma, beta) with qaoa_lbfgs_minimize on -E, each evaluation being
+ * one qaoa_gradient call.  gamma, beta (host [p], in-out) hold the start and
+ * receive the optimum; E receives E at the optimum.  trace_x rows are
+ * (gamma, beta) of each iterate and trace_f holds E (not -E).  The handle has
+ * no current state afterwards.  Errors as qaoa_gradient and qaoa_lbfgs_minimize.
+ */
+qaoa_status qaoa_optimize(qaoa_handle h, int32_t p, double *gamma, double *beta,
+                          const qaoa_lbfgs_options *opt, double *E, int32_t *iters, int32_t *evals,
+                          double *trace_x, double *trace_f);
+
+/*
  * Kernel timing for measurement.  While enabled, every streaming pass launch
  * (forward, turn and backward passes of qaoa_statevector / qaoa_evaluate /
  * qaoa_gradient) is bracketed by a pair of HIP events on the handle's stream.

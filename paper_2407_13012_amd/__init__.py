@@ -12,6 +12,7 @@ from ._binding import (  # noqa: F401
     QAOA_C128,
     QAOA_C64,
     QaoaError,
+    LbfgsOptions,
     QaoaHandle,
     library_path,
     load_library,
@@ -25,6 +26,8 @@ from ._binding import (  # noqa: F401
     qaoa_get_info,
     qaoa_gradient,
     qaoa_last_error_message,
+    qaoa_lbfgs_minimize,
+    qaoa_optimize,
     qaoa_pass_plan,
     qaoa_profile_enable,
     qaoa_profile_read,

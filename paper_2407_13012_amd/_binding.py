@@ -17,6 +17,17 @@ _LIB_PATH = os.path.join(_HERE, "libqaoa.so")
 _lib: Optional[ctypes.CDLL] = None
 
 
+class LbfgsOptions(ctypes.Structure):
+    """Mirror of qaoa_lbfgs_options."""
+    _fields_ = [("max_iter", ctypes.c_int32), ("history", ctypes.c_int32), ("gtol", ctypes.c_double),
+                ("ftol", ctypes.c_double), ("max_evals", ctypes.c_int32)]
+
+
+OBJECTIVE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                ctypes.c_void_p)
+
+
 def library_path() -> str:
     return _LIB_PATH
 
@@ -55,6 +66,9 @@ def load_library() -> ctypes.CDLL:
         "qaoa_gradient": [vp, i32, vp, vp, pd, vp, vp],
         "qaoa_sample": [vp, i64, u64, vp, vp, i32],
         "qaoa_pass_plan": [i32, i32, i32, pi32, vp, vp],
+        "qaoa_lbfgs_minimize": [i32, vp, OBJECTIVE_FN, vp, ctypes.POINTER(LbfgsOptions), pd,
+                                pi32, pi32, vp, vp],
+        "qaoa_optimize": [vp, i32, vp, vp, ctypes.POINTER(LbfgsOptions), pd, pi32, pi32, vp, vp],
         "qaoa_profile_enable": [vp, i32],
         "qaoa_profile_read": [vp, i32, ctypes.POINTER(i64), pd, pd],
     }
@@ -235,6 +249,68 @@ def qaoa_pass_plan(n: int, precision="c128"):
     return [(int(tb[i]), int(tg[i])) for i in range(cnt.value)]
 
 
+def _options(max_iter, history, gtol, ftol, max_evals):
+    return LbfgsOptions(int(max_iter), int(history), float(gtol), float(ftol), int(max_evals))
+
+
+def qaoa_lbfgs_minimize(fun, x0, max_iter=100, history=10, gtol=1e-8, ftol=0.0, max_evals=1000,
+                        trace=False):
+    """Minimise fun(x) -> (f, g) from x0 with the library's L-BFGS.
+    Returns (x, f, iters, evals[, trace_x, trace_f])."""
+    lib = load_library()
+    x = np.ascontiguousarray(x0, dtype=np.float64).copy()
+    dim = x.size
+    err = []
+
+    def cb(xp, fp, gp, _user):
+        try:
+            xv = np.ctypeslib.as_array(xp, shape=(dim,)).copy()
+            f, g = fun(xv)
+            fp[0] = float(f)
+            gv = np.asarray(g, dtype=np.float64)
+            for i in range(dim):
+                gp[i] = gv[i]
+            return 0
+        except Exception as e:  # stop the optimiser; re-raised below
+            err.append(e)
+            return 1
+
+    cfun = OBJECTIVE_FN(cb)
+    fx = ctypes.c_double()
+    it, ev = ctypes.c_int32(), ctypes.c_int32()
+    tx = np.zeros((max_iter + 1, dim)) if trace else None
+    tf = np.zeros(max_iter + 1) if trace else None
+    opt = _options(max_iter, history, gtol, ftol, max_evals)
+    st = lib.qaoa_lbfgs_minimize(dim, _ptr(x), cfun, None, ctypes.byref(opt), ctypes.byref(fx),
+                                 ctypes.byref(it), ctypes.byref(ev), _ptr(tx), _ptr(tf))
+    if err:
+        raise err[0]
+    _check(st, "qaoa_lbfgs_minimize")
+    if trace:
+        return x, fx.value, it.value, ev.value, tx[: it.value + 1], tf[: it.value + 1]
+    return x, fx.value, it.value, ev.value
+
+
+def qaoa_optimize(h, gamma, beta, max_iter=100, history=10, gtol=1e-8, ftol=0.0, max_evals=1000,
+                  trace=False):
+    """Maximise E(gamma, beta) with L-BFGS on the GPU gradient.
+    Returns (gamma, beta, E, iters, evals[, trace_x, trace_E])."""
+    g, b = _angles(gamma, beta)
+    g, b = g.copy(), b.copy()
+    p = g.size
+    E = ctypes.c_double()
+    it, ev = ctypes.c_int32(), ctypes.c_int32()
+    tx = np.zeros((max_iter + 1, 2 * p)) if trace else None
+    tf = np.zeros(max_iter + 1) if trace else None
+    opt = _options(max_iter, history, gtol, ftol, max_evals)
+    _check(load_library().qaoa_optimize(h, p, _ptr(g), _ptr(b), ctypes.byref(opt), ctypes.byref(E),
+                                        ctypes.byref(it), ctypes.byref(ev), _ptr(tx), _ptr(tf)),
+           "qaoa_optimize")
+    if trace:
+        return g, b, E.value, it.value, ev.value, tx[: it.value + 1], tf[: it.value + 1]
+    return g, b, E.value, it.value, ev.value
+
+
 PASS_KINDS = ("forward", "turn", "backward")
 
 
@@ -325,6 +401,9 @@ class QaoaHandle:
 
     def sample(self, shots: int, seed: int, **kw):
         return qaoa_sample(self._h, shots, seed, **kw)
+
+    def optimize(self, gamma, beta, **kw):
+        return qaoa_optimize(self._h, gamma, beta, **kw)
 
     def profile_enable(self, on: bool = True):
         qaoa_profile_enable(self._h, on)
