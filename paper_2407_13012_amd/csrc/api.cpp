@@ -212,7 +212,7 @@ double pass_bytes(qaoa_handle h, int mode, const qk::PassArgs &a)
     if (mode == qk::kFwd)
         return N * ((initd ? 0 : s) + (store ? s : 0) +
                     ((a.flags & (qk::kPhaseIn | qk::kEOut)) ? c : 0));
-    if (mode == qk::kTurn) return N * ((initd ? 0 : s) + c + (store ? s : 0));
+    if (mode == qk::kTurn || mode == qk::kTurnPhase) return N * ((initd ? 0 : s) + c + (store ? s : 0));
     return N * (2 * s + (store ? 2 * s : 0) + ((a.flags & qk::kPhaseOut) ? c : 0));
 }
 
@@ -233,7 +233,8 @@ qaoa_status run_pass(qaoa_handle h, int mode, const qk::PassArgs &a)
         HIPCHECK(h, qk::launch_pass(mode, c64(h), a, nblocks(h->n), h->stream));
         return QAOA_OK;
     }
-    qaoa_handle_s::Pending pd{mode, pass_bytes(h, mode, a), nullptr, nullptr};
+    const int kind = mode == qk::kTurnPhase ? qk::kTurn : mode;  // reported with the turn passes
+    qaoa_handle_s::Pending pd{kind, pass_bytes(h, mode, a), nullptr, nullptr};
     qaoa_status st = take_event(h, &pd.t0);
     if (st == QAOA_OK) st = take_event(h, &pd.t1);
     if (st != QAOA_OK) return st;
@@ -622,7 +623,7 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
             a.part_g = slotG(l);
             if (l == 0) a.flags |= qk::kInit | qk::kNoStore;
         }
-        if ((st = run_pass(h, qk::kTurn, a)) != QAOA_OK) return st;
+        if ((st = run_pass(h, P == 1 ? qk::kTurnPhase : qk::kTurn, a)) != QAOA_OK) return st;
     }
     // Backward sweep: layer l undoes groups (last..0); group 0 also undoes the phase.
     for (int l = p - 1; l >= 0; --l) {

@@ -90,8 +90,12 @@ __device__ __forceinline__ void stnt(float2 v, float2 *p)
 
 // ------------------------------------------------------------ tile geometry
 
-// XOR swizzle of the LDS slot: conflict-free 16 B accesses in all three arrangements.
-__device__ __forceinline__ uint32_t lds_slot(uint32_t e) { return e ^ ((e >> 4) & 15u); }
+// LDS slot of tile element e: one padding slot after every 16 elements.  In all
+// three arrangements any 16 consecutive lanes then hit distinct 16 B bank
+// groups, and the slot is additive over the thread part and the register part
+// of e, so every access is one base register plus an immediate offset.
+constexpr int kLdsSlots = kTile + kTile / 16;
+__host__ __device__ __forceinline__ constexpr uint32_t lds_slot(uint32_t e) { return e + (e >> 4); }
 
 template <int ARR>
 __host__ __device__ __forceinline__ constexpr uint32_t elem(uint32_t lane, uint32_t wave,
@@ -285,11 +289,13 @@ __device__ __forceinline__ void adj_stage(V (&f)[16], V (&l)[16], R m, uint32_t 
 template <int FROM, int TO, typename V>
 __device__ __forceinline__ void xpose(V (&v)[16], V *lds, uint32_t lane, uint32_t wave)
 {
+    V *wr = lds + lds_slot(elem<FROM>(lane, wave, 0));
+    V *rd = lds + lds_slot(elem<TO>(lane, wave, 0));
 #pragma unroll
-    for (int r = 0; r < 16; ++r) lds[lds_slot(elem<FROM>(lane, wave, r))] = v[r];
+    for (int r = 0; r < 16; ++r) wr[lds_slot(elem<FROM>(0, 0, r))] = v[r];
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = lds[lds_slot(elem<TO>(lane, wave, r))];
+    for (int r = 0; r < 16; ++r) v[r] = rd[lds_slot(elem<TO>(0, 0, r))];
     __syncthreads();
 }
 
@@ -333,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
 {
     using V = typename Tr<R>::V;
     using CT = typename Tr<R>::CT;
-    __shared__ V lds[kTile];
+    __shared__ V lds[kLdsSlots];
 
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     const uint64_t b = blockIdx.x;
@@ -363,7 +369,24 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
     double accE = 0.0, accB = 0.0, accG = 0.0;
     const V zero = {(R)0, (R)0};
 
-    if constexpr (MODE == kFwd || MODE == kTurn) {
+    // All global loads of the pass are issued up front (cost entries first);
+    // loads placed after the arithmetic were found to serialise with it.
+    constexpr bool TURN = MODE == kTurn || MODE == kTurnPhase;
+    // which optional steps this launch performs (compile-time where the mode decides)
+    const bool phaseIn = MODE == kTurnPhase || (MODE == kFwd && (a.flags & kPhaseIn));
+    const bool phaseOut = MODE == kTurnPhase || (MODE == kBwd && (a.flags & kPhaseOut));
+    const bool costC = TURN || phaseOut || (MODE == kFwd && (a.flags & kEOut));
+    CT cin[16], cv[16];
+    if (phaseIn) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) cin[r] = VA(r) ? ld(&cost[ZA(r)], strm) : (CT)0;
+    }
+    if (costC) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) cv[r] = VC(r) ? ld(&cost[ZC(r)], strm) : (CT)0;
+    }
+
+    if constexpr (MODE == kFwd || TURN) {
         V v[16];
         if (a.flags & kInit) {
             const V a0 = {(R)a.amp0, (R)0};
@@ -373,12 +396,12 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
 #pragma unroll
             for (int r = 0; r < 16; ++r) v[r] = VA(r) ? ld(&psi[ZA(r)], strm) : zero;
         }
-        if (a.flags & kPhaseIn) {
+        if (phaseIn) {
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 if (VA(r)) {
                     R c, s;
-                    phase_cs(-a.gamma_in, ld(&cost[ZA(r)], strm), c, s);
+                    phase_cs(-a.gamma_in, cin[r], c, s);
                     v[r] = cmul(v[r], c, s);
                 }
         }
@@ -395,8 +418,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
         if constexpr (MODE == kFwd) {
             if (a.flags & kEOut) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    if (VC(r)) accE += (double)ld(&cost[ZC(r)], strm) * norm2(v[r]);
+                for (int r = 0; r < 16; ++r) accE += (double)cv[r] * norm2(v[r]);
             }
             if (!(a.flags & kNoStore)) {
 #pragma unroll
@@ -405,13 +427,11 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
             }
         } else {
             // v is the final state phi on this tile: E, lam = C phi, then undo the
-            // group on both, visiting the register arrangements C, B, A, and
-            // return lam to arrangement C (where C is already loaded) to store it.
+            // group on both, visiting the register arrangements C, B, A; lam is
+            // stored from A (from C when the phase is undone too).
             V l[16];
-            CT cv[16];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                cv[r] = VC(r) ? ld(&cost[ZC(r)], strm) : (CT)0;
                 accE += (double)cv[r] * norm2(v[r]);
                 l[r] = vscale(v[r], (R)cv[r]);
             }
@@ -426,24 +446,30 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
             xpose<1, 0>(l, lds, lane, wave);
             adj_stage<0, TM>(v, l, mb, tmask, sig2, f2, accB);
             const R sb = (R)a.scl_b;
-            xpose<0, 2>(l, lds, lane, wave);
-#pragma unroll
-            for (int r = 0; r < 16; ++r) l[r] = vscale(l[r], sb);
-            if (a.flags & kPhaseOut) {
+            if constexpr (MODE == kTurnPhase) {
+                xpose<0, 2>(l, lds, lane, wave);
                 xpose<0, 2>(v, lds, lane, wave);
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
+                for (int r = 0; r < 16; ++r) {
+                    l[r] = vscale(l[r], sb);
                     if (VC(r)) {
                         accG += (double)cv[r] * imcx(l[r], vscale(v[r], sb));
                         R c, s;
                         phase_cs(a.gamma_out, cv[r], c, s);
                         l[r] = cmul(l[r], c, s);
                     }
-            }
-            if (!(a.flags & kNoStore)) {
+                }
+                if (!(a.flags & kNoStore)) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    if (VC(r)) st(l[r], &lam[ZC(r)], strm);
+                    for (int r = 0; r < 16; ++r)
+                        if (VC(r)) st(l[r], &lam[ZC(r)], strm);
+                }
+            } else {
+                if (!(a.flags & kNoStore)) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        if (VA(r)) st(vscale(l[r], sb), &lam[ZA(r)], strm);
+                }
             }
         }
     } else {
@@ -470,14 +496,13 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
             f[r] = vscale(f[r], sb);
             l[r] = vscale(l[r], sb);
         }
-        if (a.flags & kPhaseOut) {
+        if (phaseOut) {
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 if (VC(r)) {
-                    const CT cv = ld(&cost[ZC(r)], strm);
-                    accG += (double)cv * imcx(l[r], f[r]);
+                    accG += (double)cv[r] * imcx(l[r], f[r]);
                     R c, s;
-                    phase_cs(a.gamma_out, cv, c, s);
+                    phase_cs(a.gamma_out, cv[r], c, s);
                     f[r] = cmul(f[r], c, s);
                     l[r] = cmul(l[r], c, s);
                 }
@@ -498,9 +523,9 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
 
     // Fixed-order block reductions; one partial per workgroup.
     double *red = (double *)lds;  // every LDS read above completed before the last barrier
-    const bool wantE = (MODE == kTurn) || (MODE == kFwd && (a.flags & kEOut));
+    const bool wantE = TURN || (MODE == kFwd && (a.flags & kEOut));
     const bool wantB = MODE != kFwd;
-    const bool wantG = MODE != kFwd && (a.flags & kPhaseOut);
+    const bool wantG = phaseOut;
     if (wantE) {
         const double s = block_sum(accE, red);
         if (tid == 0) a.part_e[b] = s;
@@ -850,6 +875,8 @@ static void launch_pass_t(int mode, const PassArgs &a, dim3 grid, hipStream_t s)
 {
     if (mode == kFwd) hipLaunchKernelGGL((k_pass<R, kFwd, TM>), grid, dim3(kThreads), 0, s, a);
     else if (mode == kTurn) hipLaunchKernelGGL((k_pass<R, kTurn, TM>), grid, dim3(kThreads), 0, s, a);
+    else if (mode == kTurnPhase)
+        hipLaunchKernelGGL((k_pass<R, kTurnPhase, TM>), grid, dim3(kThreads), 0, s, a);
     else hipLaunchKernelGGL((k_pass<R, kBwd, TM>), grid, dim3(kThreads), 0, s, a);
 }
 
