@@ -87,6 +87,19 @@ qaoa_status qaoa_create_qubo(int32_t n, int64_t m, const int32_t *pairs, const d
                              const double *h, double offset, int32_t precision, void *stream,
                              qaoa_handle *out);
 
+/*
+ * Create a handle for a general 0-1 polynomial (Eq. (2)): term k has the
+ * one-hot mask masks[k] = sum_{i in t_k} 2^i and weight w[k], and is active in
+ * z iff (z AND masks[k]) == masks[k].  C(z) = offset + sum of the active
+ * weights, added in term order.  A zero mask is a constant term.
+ *   L       number of terms, L >= 0
+ *   masks   host uint64 [L], every mask < 2^n
+ *   w       host fp64 [L], finite
+ * Other arguments and errors as qaoa_create_maxcut.
+ */
+qaoa_status qaoa_create_poly(int32_t n, int64_t L, const uint64_t *masks, const double *w,
+                             double offset, int32_t precision, void *stream, qaoa_handle *out);
+
 /* Release every device buffer and the private stream.  NULL is a no-op. */
 qaoa_status qaoa_destroy(qaoa_handle h);
 

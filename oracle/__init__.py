@@ -126,9 +126,14 @@ def cost_poly(n: int, masks, weights) -> np.ndarray:
 
 
 def cost_of(instance) -> np.ndarray:
-    """Cost diagonal of a qaoa_inputs.MaxCut or qaoa_inputs.Qubo instance."""
+    """Cost diagonal of a qaoa_inputs.MaxCut, Qubo or Poly instance."""
     if hasattr(instance, "edges"):
         return cost_maxcut(instance.n, instance.edges, instance.weights)
+    if hasattr(instance, "masks"):
+        # the constant is a term whose (empty) mask is always active, added first
+        masks = np.concatenate([[0], np.asarray(instance.masks, np.uint64)]).astype(np.uint64)
+        w = np.concatenate([[instance.offset], instance.weights])
+        return cost_poly(instance.n, masks, w)
     return cost_qubo(instance.n, instance.pairs, instance.J, instance.h, instance.offset)
 
 

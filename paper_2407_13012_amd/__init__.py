@@ -19,6 +19,7 @@ from ._binding import (  # noqa: F401
     qaoa_cost_diagonal,
     qaoa_cost_extrema,
     qaoa_create_maxcut,
+    qaoa_create_poly,
     qaoa_create_qubo,
     qaoa_destroy,
     qaoa_evaluate,

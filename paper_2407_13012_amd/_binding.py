@@ -56,6 +56,7 @@ def load_library() -> ctypes.CDLL:
     sigs = {
         "qaoa_create_maxcut": [i32, i64, vp, vp, i32, vp, pvp],
         "qaoa_create_qubo": [i32, i64, vp, vp, vp, d, i32, vp, pvp],
+        "qaoa_create_poly": [i32, i64, vp, vp, d, i32, vp, pvp],
         "qaoa_destroy": [vp],
         "qaoa_get_info": [vp, pi32, pi32],
         "qaoa_cost_diagonal": [vp, vp, i32],
@@ -147,6 +148,19 @@ def qaoa_create_qubo(n: int, pairs, J, h=None, offset: float = 0.0, precision="c
     _check(lib.qaoa_create_qubo(int(n), pr.shape[0], _ptr(pr), _ptr(Jv) if Jv.size else None,
                                 _ptr(hv), float(offset), _PREC[precision], _stream(stream),
                                 ctypes.byref(out)), "qaoa_create_qubo")
+    return out
+
+
+def qaoa_create_poly(n: int, masks, weights, offset: float = 0.0, precision="c128", stream=None):
+    lib = load_library()
+    m = np.ascontiguousarray(masks, dtype=np.uint64).reshape(-1)
+    w = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+    if m.shape != w.shape:
+        raise ValueError("masks and weights must have the same length")
+    out = ctypes.c_void_p()
+    _check(lib.qaoa_create_poly(int(n), m.size, _ptr(m) if m.size else None, _ptr(w) if w.size else None,
+                                float(offset), _PREC[precision], _stream(stream), ctypes.byref(out)),
+           "qaoa_create_poly")
     return out
 
 
@@ -351,9 +365,15 @@ class QaoaHandle:
         return cls(qaoa_create_qubo(n, pairs, J, h, offset, precision, stream))
 
     @classmethod
+    def poly(cls, n, masks, weights, offset=0.0, precision="c128", stream=None):
+        return cls(qaoa_create_poly(n, masks, weights, offset, precision, stream))
+
+    @classmethod
     def from_instance(cls, inst, precision="c128", stream=None):
         if hasattr(inst, "edges"):
             return cls.maxcut(inst.n, inst.edges, inst.weights, precision, stream)
+        if hasattr(inst, "masks"):
+            return cls.poly(inst.n, inst.masks, inst.weights, inst.offset, precision, stream)
         return cls.qubo(inst.n, inst.pairs, inst.J, inst.h, inst.offset, precision, stream)
 
     @property

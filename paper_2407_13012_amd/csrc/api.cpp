@@ -438,6 +438,40 @@ qaoa_status qaoa_create_qubo(int32_t n, int64_t m, const int32_t *pairs, const d
     return QAOA_OK;
 }
 
+qaoa_status qaoa_create_poly(int32_t n, int64_t L, const uint64_t *masks, const double *w,
+                             double offset, int32_t precision, void *stream, qaoa_handle *out)
+{
+    if (n < 1 || n > QAOA_MAX_QUBITS)
+        return fail(QAOA_ERR_INVALID_ARGUMENT, "n must be in [1, QAOA_MAX_QUBITS]");
+    if (L < 0) return fail(QAOA_ERR_INVALID_ARGUMENT, "L must be >= 0");
+    if (L > 0 && (!masks || !w)) return fail(QAOA_ERR_INVALID_ARGUMENT, "mask or weight array is NULL");
+    if (!std::isfinite(offset)) return fail(QAOA_ERR_INVALID_ARGUMENT, "offset must be finite");
+    const uint64_t lim = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+    for (int64_t k = 0; k < L; ++k) {
+        if (masks[k] & ~lim) {
+            set_err("term %s%lld uses a variable outside [0, n)", "", (long long)k);
+            return QAOA_ERR_INVALID_ARGUMENT;
+        }
+        if (!std::isfinite(w[k])) return fail(QAOA_ERR_INVALID_ARGUMENT, "weights must be finite");
+    }
+    qaoa_handle h = nullptr;
+    qaoa_status st = create_common(n, precision, stream, out, &h);
+    if (st != QAOA_OK) return st;
+    st = build_cost(h, {{masks, (size_t)L * sizeof(uint64_t)}, {w, (size_t)L * sizeof(double)}},
+                    [&](std::vector<void *> &d) {
+                        return qk::launch_cost_poly(c64(h), h->cost, n, L, (const uint64_t *)d[0],
+                                                    (const double *)d[1], offset, h->stream);
+                    });
+    if (st != QAOA_OK) {
+        std::string keep = g_err;
+        qaoa_destroy(h);
+        g_err = keep;
+        return st;
+    }
+    *out = h;
+    return QAOA_OK;
+}
+
 qaoa_status qaoa_destroy(qaoa_handle h)
 {
     if (!h) return QAOA_OK;

@@ -286,6 +286,36 @@ __device__ __forceinline__ void adj_stage(V (&f)[16], V (&l)[16], R m, uint32_t 
     }
 }
 
+// Sum over the target bits owned by arrangement ARR of Im<lam|X_j|phi> on the
+// register pairs, times w (the product of the factors both vectors miss).
+template <int ARR, typename V>
+__device__ __forceinline__ void beta_terms(const V (&f)[16], const V (&l)[16], uint32_t tmask,
+                                           double w, double &accB)
+{
+    double ps = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if ((tmask >> regbit<ARR>(q)) & 1u) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (!(r & (1 << q))) {
+                    const int r1 = r | (1 << q);
+                    ps += imcx(l[r], f[r1]) + imcx(l[r1], f[r]);
+                }
+        }
+    }
+    accB = fma(w, ps, accB);
+}
+
+__host__ __device__ __forceinline__ int popc(uint32_t x) { return __builtin_popcount(x); }
+
+__device__ __forceinline__ double upow(double f, int k)
+{
+    double r = 1.0;
+    for (int i = 0; i < k; ++i) r *= f;
+    return r;
+}
+
 template <int FROM, int TO, typename V>
 __device__ __forceinline__ void xpose(V (&v)[16], V *lds, uint32_t lane, uint32_t wave)
 {
@@ -435,7 +465,42 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
                 accE += (double)cv[r] * norm2(v[r]);
                 l[r] = vscale(v[r], (R)cv[r]);
             }
+            // Materialise the E sum here: left to the compiler it is sunk to its use
+            // after the backward stages, keeping phi and C live (register spills).
+            asm volatile("" : "+v"(accE));
             const R mb = (R)a.mul_b;
+            const R sb = (R)a.scl_b;
+            if constexpr (MODE == kTurn) {
+                // <lam|X_j|phi> of an arrangement's bits is taken at its entry, where
+                // both vectors sit at the same point.  Arrangement C: the final point.
+                // Then undo C's rotations on lam only; phi before stage C is still in
+                // LDS from the forward B->C transpose, so it is re-read, not recomputed.
+                const int kA = popc(tmask & (15u << 6)), kB = popc(tmask & 15u);
+                const int kC = popc(tmask & ((3u << 4) | (3u << 10)));
+                const double ff = a.fac_f, fb = a.fac_b;
+                beta_terms<2>(v, l, tmask, 1.0, accB);
+                mix_stage<2, TM>(l, mb, tmask);
+                {
+                    const V *rd = lds + lds_slot(elem<1>(lane, wave, 0));
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) v[r] = rd[lds_slot(elem<1>(0, 0, r))];
+                    __syncthreads();
+                }
+                xpose<2, 1>(l, lds, lane, wave);
+                // lam misses fb^kC, phi (forward stages A, B) misses ff^(kA+kB)
+                beta_terms<1>(v, l, tmask, upow(fb, kC) * upow(ff, kA + kB), accB);
+                mix_stage<1, TM>(l, mb, tmask);
+                mix_stage<1, TM>(v, mb, tmask);
+                xpose<1, 0>(v, lds, lane, wave);
+                xpose<1, 0>(l, lds, lane, wave);
+                beta_terms<0>(v, l, tmask, upow(fb, kC + 2 * kB) * upow(ff, kA + kB), accB);
+                mix_stage<0, TM>(l, mb, tmask);
+                if (!(a.flags & kNoStore)) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        if (VA(r)) st(vscale(l[r], sb), &lam[ZA(r)], strm);
+                }
+            } else {
             const double f2 = a.fac_b * a.fac_b;
             double sig2 = 1.0;
             adj_stage<2, TM>(v, l, mb, tmask, sig2, f2, accB);
@@ -445,8 +510,6 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
             xpose<1, 0>(v, lds, lane, wave);
             xpose<1, 0>(l, lds, lane, wave);
             adj_stage<0, TM>(v, l, mb, tmask, sig2, f2, accB);
-            const R sb = (R)a.scl_b;
-            if constexpr (MODE == kTurnPhase) {
                 xpose<0, 2>(l, lds, lane, wave);
                 xpose<0, 2>(v, lds, lane, wave);
 #pragma unroll
@@ -463,12 +526,6 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
 #pragma unroll
                     for (int r = 0; r < 16; ++r)
                         if (VC(r)) st(l[r], &lam[ZC(r)], strm);
-                }
-            } else {
-                if (!(a.flags & kNoStore)) {
-#pragma unroll
-                    for (int r = 0; r < 16; ++r)
-                        if (VA(r)) st(vscale(l[r], sb), &lam[ZA(r)], strm);
                 }
             }
         }
@@ -667,6 +724,25 @@ __global__ __launch_bounds__(kThreads) void k_cost_qubo(CT *C, uint64_t N, int n
                 const bool on = (z >> i) & 1ull;
                 acc = on ? acc + h[i] : acc;
             }
+        C[z] = (CT)acc;
+    }
+}
+
+// General 0-1 polynomial of Eq. (2): term k (mask m_k, weight w_k) is active in
+// z iff every variable of its mask is 1, (z AND m_k) == m_k; terms are added in
+// the given order after the offset.
+template <typename CT>
+__global__ __launch_bounds__(kThreads) void k_cost_poly(CT *C, uint64_t N, int64_t L,
+                                                        const uint64_t *masks, const double *w,
+                                                        double offset)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kThreads;
+    for (uint64_t z = (uint64_t)blockIdx.x * kThreads + threadIdx.x; z < N; z += stride) {
+        double acc = offset;
+        for (int64_t k = 0; k < L; ++k) {
+            const uint64_t m = masks[k];
+            acc = ((z & m) == m) ? acc + w[k] : acc;
+        }
         C[z] = (CT)acc;
     }
 }
@@ -923,6 +999,19 @@ hipError_t launch_cost_qubo(bool c64, void *C, int n, int64_t m, const int32_t *
     else
         hipLaunchKernelGGL(k_cost_qubo<double>, dim3(grid_for(N)), dim3(kThreads), 0, s,
                            (double *)C, N, n, m, pairs, J, h, offset);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost_poly(bool c64, void *C, int n, int64_t L, const uint64_t *masks,
+                            const double *w, double offset, hipStream_t s)
+{
+    const uint64_t N = 1ull << n;
+    if (c64)
+        hipLaunchKernelGGL(k_cost_poly<float>, dim3(grid_for(N)), dim3(kThreads), 0, s,
+                           (float *)C, N, L, masks, w, offset);
+    else
+        hipLaunchKernelGGL(k_cost_poly<double>, dim3(grid_for(N)), dim3(kThreads), 0, s,
+                           (double *)C, N, L, masks, w, offset);
     return hipGetLastError();
 }
 

@@ -97,13 +97,20 @@ std::vector<PassPlan> plan_passes(int n, bool c64)
     int nc = kTileBits - x[0];          // next non-crossing bit to hand out
     int cr = std::max(page, kTileBits); // next crossing bit to hand out
     if (n <= page) cr = n;
-    out[0].target_bits = low_mask(kTileBits - x[0]);
-    for (int j = 0; j < x[0]; ++j) out[0].target_bits |= 1ull << cr++;
+    // Crossing bits are handed out in ascending blocks: pass 1 first, then
+    // pass 0, then passes 2..  (the order measured fastest at n = 32).
+    std::vector<int> order;
+    if (P1 >= 1) order.push_back(1);
+    order.push_back(0);
+    for (int i = 2; i <= P1; ++i) order.push_back(i);
+    std::vector<uint64_t> crossing(P1 + 1, 0);
+    for (int i : order)
+        for (int j = 0; j < x[i]; ++j) crossing[i] |= 1ull << cr++;
+    out[0].target_bits = low_mask(kTileBits - x[0]) | crossing[0];
     out[0].tile_bits = out[0].target_bits;
     for (int i = 1; i <= P1; ++i) {
-        uint64_t tg = 0;
+        uint64_t tg = crossing[i];
         for (int j = 0; j < k[i] - x[i]; ++j) tg |= 1ull << nc++;
-        for (int j = 0; j < x[i]; ++j) tg |= 1ull << cr++;
         out[i].target_bits = tg;
         out[i].tile_bits = tg | low_mask(kTileBits - k[i]);
     }

@@ -93,6 +93,8 @@ hipError_t launch_cost_maxcut(bool c64, void *C, int n, int64_t m, const int32_t
                               const double *w, hipStream_t s);
 hipError_t launch_cost_qubo(bool c64, void *C, int n, int64_t m, const int32_t *pairs,
                             const double *J, const double *h, double offset, hipStream_t s);
+hipError_t launch_cost_poly(bool c64, void *C, int n, int64_t L, const uint64_t *masks,
+                            const double *w, double offset, hipStream_t s);
 hipError_t launch_fill_plus(bool c64, void *psi, int n, hipStream_t s);
 hipError_t launch_expect(bool c64, const void *psi, const void *C, int n, double *parts,
                          hipStream_t s);

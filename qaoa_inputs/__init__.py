@@ -138,6 +138,30 @@ def qubo_blocks(n: int, block: int, p_edge: float, seed) -> Qubo:
     return Qubo(n=n, pairs=pairs, J=J, h=h)
 
 
+@dataclasses.dataclass
+class Poly:
+    """General 0-1 polynomial (Eq. 2): C(z) = offset + sum_k w_k [z AND m_k == m_k]."""
+    n: int
+    masks: np.ndarray     # uint64 (L,)
+    weights: np.ndarray   # float64 (L,)
+    offset: float = 0.0
+
+    @property
+    def m(self) -> int:
+        return int(self.masks.shape[0])
+
+
+def poly_random(n: int, L: int, max_degree: int, seed, offset: float = 0.0) -> Poly:
+    """L random terms of degree 1..max_degree on distinct variables, weights N(0,1)."""
+    rng = np.random.default_rng(seed)
+    masks = np.zeros(L, dtype=np.uint64)
+    for k in range(L):
+        d = int(rng.integers(1, max_degree + 1))
+        vs = rng.choice(n, size=min(d, n), replace=False)
+        masks[k] = np.uint64(sum(1 << int(v) for v in vs))
+    return Poly(n=n, masks=masks, weights=rng.standard_normal(L), offset=offset)
+
+
 def _draw_weights(rng, m, kind, wlow, whigh):
     if kind == "unit":
         return None
