@@ -29,6 +29,40 @@ METRIC = "grad evals/s + HBM GB/s at n=32 p=3; time-to-ratio learned vs plain in
 HBM_PEAK_GBS = 8000.0
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_pass_traffic_qubo32_p3_c128.md")
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2407_13012_amd", "csrc", f)
+                   for f in ("kernels.hip", "plan.cpp", "api.cpp", "qaoa_internal.h")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kind: str):
+    """HBM bytes per launch of one pass kind from the committed rocprofv3 counter
+    summary, or None when it is missing or was taken on different kernel sources."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel sources sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals[f"{kind} HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def model_bytes_per_amp(n: int, p: int, s: int, c: int) -> float:
     """Per-amplitude bytes of one E+G under the pass model p(6 P s + 2 c) + c - 2 s
     with P = ceil(n / kmax) passes per mixer layer (kmax = 13 for 16-byte
@@ -141,7 +175,7 @@ def main() -> int:
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
-        "traffic": None,
+        "traffic": recorded_traffic(dom) if (args.n == 32 and args.precision == "c128") else None,
         "bytes_per_launch": dk["bytes"] / max(dk["launches"], 1),
         "avg_launch_ms": dk["ms"] / max(dk["launches"], 1),
     }
