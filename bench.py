@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_pass_traffic_qubo32_p3_c128.md")
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2407_13012_amd", "csrc", f)
-                   for f in ("kernels.hip", "plan.cpp", "api.cpp", "qaoa_internal.h")]
+                   for f in ("kernels.hip", "tile_device.h", "plan.cpp", "api.cpp", "qaoa_internal.h")]
 
 
 def kernel_source_hash() -> str:

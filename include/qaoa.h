@@ -240,6 +240,71 @@ qaoa_status qaoa_profile_read(qaoa_handle h, int32_t kind, int64_t *launches, do
 qaoa_status qaoa_pass_plan(int32_t n, int32_t precision, int32_t cap, int32_t *npasses,
                            uint64_t *tile_bits, uint64_t *target_bits);
 
+/*
+ * Batched engine: many small weighted MaxCut instances, each optimised with
+ * Adam on its 2p angles, in one persistent launch (Sec. V-C: parameter
+ * optimisation driven by the simulator's gradients; here every instance's loop
+ * runs on the device).
+ *
+ * A fixed grid of workgroups takes instances from an on-device queue, largest
+ * n first.  A workgroup runs one instance start to end in its own scratch slot
+ * (state, adjoint vector and cost diagonal, 2^nmax amplitudes each, complex128):
+ * cost diagonal (as qaoa_create_maxcut), then `steps` Adam ascent steps on
+ * E(gamma, beta) / sum_k |w_k|, each step one expectation + adjoint gradient
+ * with the same tiled passes as qaoa_gradient, then E at the final angles.
+ * Adam (Kingma & Ba 2015): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * theta += lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps), t = 1, 2, ...
+ * The queue-reset kernel and the engine are captured once in a hipGraph and
+ * replayed by every qaoa_batch_run.
+ */
+typedef struct qaoa_batch_s *qaoa_batch;
+
+/* Largest qubit count of a batched instance. */
+#define QAOA_BATCH_MAX_QUBITS 24
+
+typedef struct {
+    int32_t steps;      /* Adam steps per instance, >= 0 */
+    double lr;          /* step size, > 0 */
+    double beta1;       /* first-moment decay, [0, 1) */
+    double beta2;       /* second-moment decay, [0, 1) */
+    double eps;         /* > 0 */
+    int32_t workgroups; /* persistent workgroups (scratch slots); 0 = 2 per compute unit */
+    int32_t max_group;  /* most qubits rotated per mixer pass after the first, 1..10 */
+    int32_t use_graph;  /* nonzero: replay a captured hipGraph; 0: launch eagerly */
+    int32_t group_by_n[QAOA_BATCH_MAX_QUBITS + 1]; /* per-n override of max_group; 0 = none */
+} qaoa_batch_options;
+
+/*
+ * Create a batch of `count` MaxCut instances of depth p (1 <= p <= 16).
+ *   n             host int32 [count], each in [2, QAOA_BATCH_MAX_QUBITS]
+ *   edge_offsets  host int64 [count + 1], edge_offsets[0] = 0, non-decreasing;
+ *                 instance i owns edges [edge_offsets[i], edge_offsets[i+1])
+ *   edges         host int32 [E][2] with vertex indices local to the instance
+ *                 (0 <= u, v < n[i], u != v); E = edge_offsets[count]
+ *   w             host fp64 [E], finite; NULL means unit weights
+ *   opt           NULL means {100, 0.05, 0.9, 0.999, 1e-8, 0, 10, 1, {0}}
+ * Allocates all device memory (instances, angles, scratch slots) on the current
+ * device and its own non-blocking stream; nothing is allocated by qaoa_batch_run.
+ * Errors: INVALID_ARGUMENT, OUT_OF_MEMORY (slots exceed free memory), DEVICE.
+ */
+qaoa_status qaoa_batch_create(int32_t count, const int32_t *n, const int64_t *edge_offsets,
+                              const int32_t *edges, const double *w, int32_t p,
+                              const qaoa_batch_options *opt, qaoa_batch *out);
+
+/*
+ * Optimise every instance from the start angles gamma0, beta0 (host fp64
+ * [count][p], finite).  Outputs (host, each may be NULL): gamma, beta
+ * [count][p] the final angles; e_first [count] E at the start angles;
+ * e_last [count] E at the final angles.  Synchronous.  Results depend only on
+ * the inputs (each instance is processed by one workgroup in a fixed order).
+ * Errors: INVALID_ARGUMENT; DEVICE (the batch is then unusable).
+ */
+qaoa_status qaoa_batch_run(qaoa_batch b, const double *gamma0, const double *beta0, double *gamma,
+                           double *beta, double *e_first, double *e_last);
+
+/* Release the batch's device memory, graph and stream.  NULL is accepted. */
+qaoa_status qaoa_batch_destroy(qaoa_batch b);
+
 /* Static English description of a status code. */
 const char *qaoa_status_string(qaoa_status s);
 

@@ -2,7 +2,7 @@
 
 A plain FP64 implementation (``qaoa_oracle.c``) of what the GPU library
 computes: cost diagonal, initial state, phase and mixer layers, expectation,
-adjoint gradient and sampling.  Only the test-suite, the package smoke check and
+adjoint gradient and sampling, plus the Adam loop of the batched optimiser.  Only the test-suite, the package smoke check and
 the benchmark's CPU-baseline leg may import this module.  The product path never
 does, and this module never imports the product package.
 
@@ -209,3 +209,45 @@ def sample(n: int, psi: np.ndarray, C: Optional[np.ndarray], shots: int, seed: i
     if rc != 0:
         raise ValueError("oracle_sample failed (zero norm or out of memory)")
     return z, cost
+
+
+def adam_ascent(fun, x0, steps: int, lr: float, beta1: float, beta2: float, eps: float):
+    """Adam (Kingma & Ba 2015, Algorithm 1) on the ascent direction of fun.
+
+    fun(x) -> (f, g) with g the gradient of f.  For t = 1..steps, with g_t the
+    gradient at x_{t-1}: m_t = beta1 m_{t-1} + (1 - beta1) g_t,
+    v_t = beta2 v_{t-1} + (1 - beta2) g_t^2, m^ = m_t / (1 - beta1^t),
+    v^ = v_t / (1 - beta2^t), x_t = x_{t-1} + lr m^ / (sqrt(v^) + eps).
+    Returns (x_steps, f(x_0), f(x_steps))."""
+    x = np.array(x0, dtype=np.float64, copy=True)
+    m = np.zeros_like(x)
+    v = np.zeros_like(x)
+    f_first = None
+    for t in range(1, steps + 1):
+        f, g = fun(x)
+        g = np.asarray(g, dtype=np.float64)
+        if f_first is None:
+            f_first = f
+        m = beta1 * m + (1.0 - beta1) * g
+        v = beta2 * v + (1.0 - beta2) * g * g
+        mh = m / (1.0 - beta1 ** t)
+        vh = v / (1.0 - beta2 ** t)
+        x = x + lr * mh / (np.sqrt(vh) + eps)
+    f_last, _ = fun(x)
+    if f_first is None:
+        f_first = f_last
+    return x, f_first, f_last
+
+
+def adam_qaoa(n: int, C: np.ndarray, gamma, beta, steps: int, lr: float = 0.05, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8, scale: float = 1.0):
+    """Adam ascent on scale * E(gamma, beta) with the adjoint gradient above.
+    Returns (gamma, beta, E at the start angles, E at the final angles)."""
+    p = len(gamma)
+
+    def fun(x):
+        E, dg, db = gradient(n, C, x[:p], x[p:])
+        return E, scale * np.concatenate([dg, db])
+
+    x, e0, e1 = adam_ascent(fun, np.concatenate([_f64(gamma), _f64(beta)]), steps, lr, beta1, beta2, eps)
+    return x[:p], x[p:], e0, e1

@@ -14,6 +14,12 @@ from ._binding import (  # noqa: F401
     QaoaError,
     LbfgsOptions,
     QaoaHandle,
+    QaoaBatch,
+    BatchOptions,
+    batch_options,
+    qaoa_batch_create,
+    qaoa_batch_destroy,
+    qaoa_batch_run,
     library_path,
     load_library,
     qaoa_cost_diagonal,
@@ -38,4 +44,4 @@ from ._binding import (  # noqa: F401
 )
 
 __all__ = [name for name in dir() if name.startswith("qaoa_")] + [
-    "QaoaHandle", "QaoaError", "QAOA_C128", "QAOA_C64", "load_library", "library_path"]
+    "QaoaHandle", "QaoaBatch", "BatchOptions", "batch_options", "QaoaError", "QAOA_C128", "QAOA_C64", "load_library", "library_path"]

@@ -23,6 +23,17 @@ class LbfgsOptions(ctypes.Structure):
                 ("ftol", ctypes.c_double), ("max_evals", ctypes.c_int32)]
 
 
+BATCH_MAX_QUBITS = 24
+
+
+class BatchOptions(ctypes.Structure):
+    """Mirror of qaoa_batch_options."""
+    _fields_ = [("steps", ctypes.c_int32), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("workgroups", ctypes.c_int32),
+                ("max_group", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("group_by_n", ctypes.c_int32 * (BATCH_MAX_QUBITS + 1))]
+
+
 OBJECTIVE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                 ctypes.c_void_p)
@@ -71,6 +82,9 @@ def load_library() -> ctypes.CDLL:
                                 pi32, pi32, vp, vp],
         "qaoa_optimize": [vp, i32, vp, vp, ctypes.POINTER(LbfgsOptions), pd, pi32, pi32, vp, vp],
         "qaoa_profile_enable": [vp, i32],
+        "qaoa_batch_create": [i32, vp, vp, vp, vp, i32, ctypes.POINTER(BatchOptions), pvp],
+        "qaoa_batch_run": [vp, vp, vp, vp, vp, vp, vp],
+        "qaoa_batch_destroy": [vp],
         "qaoa_profile_read": [vp, i32, ctypes.POINTER(i64), pd, pd],
     }
     for name, args in sigs.items():
@@ -325,6 +339,55 @@ def qaoa_optimize(h, gamma, beta, max_iter=100, history=10, gtol=1e-8, ftol=0.0,
     return g, b, E.value, it.value, ev.value
 
 
+def batch_options(steps=100, lr=0.05, beta1=0.9, beta2=0.999, eps=1e-8, workgroups=0, max_group=10,
+                  use_graph=True, group_by_n=None) -> BatchOptions:
+    gb = (ctypes.c_int32 * (BATCH_MAX_QUBITS + 1))()
+    for n, k in (group_by_n or {}).items():
+        gb[int(n)] = int(k)
+    return BatchOptions(int(steps), float(lr), float(beta1), float(beta2), float(eps), int(workgroups),
+                        int(max_group), 1 if use_graph else 0, gb)
+
+
+def qaoa_batch_create(graphs, p: int, options: Optional[BatchOptions] = None):
+    """graphs: sequence of objects with .n, .edges (m, 2) and .weights (m,) or None."""
+    lib = load_library()
+    count = len(graphs)
+    n = np.asarray([g.n for g in graphs], dtype=np.int32)
+    m = np.asarray([np.asarray(g.edges).reshape(-1, 2).shape[0] for g in graphs], dtype=np.int64)
+    off = np.zeros(count + 1, dtype=np.int64)
+    np.cumsum(m, out=off[1:])
+    edges = (np.concatenate([np.asarray(g.edges, dtype=np.int32).reshape(-1, 2) for g in graphs])
+             if count else np.zeros((0, 2), np.int32))
+    edges = np.ascontiguousarray(edges, dtype=np.int32)
+    unit = all(g.weights is None for g in graphs)
+    w = None if unit else np.ascontiguousarray(np.concatenate(
+        [np.ones(int(mi)) if g.weights is None else np.asarray(g.weights, dtype=np.float64).reshape(-1)
+         for g, mi in zip(graphs, m)]) if count else np.zeros(0), dtype=np.float64)
+    out = ctypes.c_void_p()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(lib.qaoa_batch_create(count, _ptr(n) if count else None, _ptr(off),
+                                 _ptr(edges) if edges.size else None, _ptr(w) if w is not None and w.size else None,
+                                 int(p), opt, ctypes.byref(out)), "qaoa_batch_create")
+    return out
+
+
+def qaoa_batch_run(b, gamma0, beta0):
+    """Run the batch from start angles [count][p]; returns (gamma, beta, e_first, e_last)."""
+    g0 = np.ascontiguousarray(gamma0, dtype=np.float64)
+    b0 = np.ascontiguousarray(beta0, dtype=np.float64)
+    if g0.shape != b0.shape or g0.ndim != 2:
+        raise ValueError("gamma0 and beta0 must both have shape (count, p)")
+    g, bb = np.empty_like(g0), np.empty_like(b0)
+    e0, e1 = np.empty(g0.shape[0]), np.empty(g0.shape[0])
+    _check(load_library().qaoa_batch_run(b, _ptr(g0), _ptr(b0), _ptr(g), _ptr(bb), _ptr(e0), _ptr(e1)),
+           "qaoa_batch_run")
+    return g, bb, e0, e1
+
+
+def qaoa_batch_destroy(b) -> None:
+    _check(load_library().qaoa_batch_destroy(b), "qaoa_batch_destroy")
+
+
 PASS_KINDS = ("forward", "turn", "backward")
 
 
@@ -431,3 +494,37 @@ class QaoaHandle:
     def profile_read(self):
         """{kind: (launches, ms, bytes)} for the forward, turn and backward passes."""
         return {k: qaoa_profile_read(self._h, i) for i, k in enumerate(PASS_KINDS)}
+
+
+class QaoaBatch:
+    """Owning wrapper of a batched-engine object (qaoa_batch_*): many MaxCut
+    instances optimised with on-device Adam in one persistent launch."""
+
+    def __init__(self, graphs, p: int, **options):
+        self.count = len(graphs)
+        self.p = int(p)
+        self.options = dict(options)
+        self._b = qaoa_batch_create(graphs, p, batch_options(**options))
+
+    def run(self, gamma0, beta0):
+        """Returns (gamma, beta, e_first, e_last) as numpy arrays."""
+        if self._b is None:
+            raise ValueError("batch is closed")
+        return qaoa_batch_run(self._b, gamma0, beta0)
+
+    def close(self):
+        if self._b is not None:
+            qaoa_batch_destroy(self._b)
+            self._b = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

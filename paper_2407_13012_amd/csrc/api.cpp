@@ -33,6 +33,11 @@ qaoa_status fail(qaoa_status st, const char *msg)
 
 }  // namespace
 
+namespace qk {
+void set_error_message(const std::string &m) { g_err = m; }
+std::string error_message() { return g_err; }
+}  // namespace qk
+
 struct qaoa_handle_s {
     int n = 0;
     int prec = QAOA_C128;

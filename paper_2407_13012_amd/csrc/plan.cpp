@@ -42,11 +42,11 @@ std::vector<std::pair<int, int>> runs_of(uint64_t m, int n)
     return r;
 }
 
-std::vector<PassPlan> plan_simple(int n)
+std::vector<PassPlan> plan_simple(int n, int kmax)
 {
     std::vector<PassPlan> out;
     out.push_back({low_mask(kTileBits), low_mask(kTileBits)});
-    const int r = n - kTileBits, P = (r + 9) / 10;
+    const int r = n - kTileBits, P = (r + kmax - 1) / kmax;
     int h = kTileBits;
     for (int i = 0; i < P; ++i) {
         const int k = r / P + (i < r % P ? 1 : 0);
@@ -72,11 +72,13 @@ bool plan_ok(int n, const std::vector<PassPlan> &pl)
 
 }  // namespace
 
-std::vector<PassPlan> plan_passes(int n, bool c64)
+std::vector<PassPlan> plan_passes(int n, bool c64, int kmax)
 {
     if (n <= kTileBits) return {{low_mask(n), low_mask(n)}};
+    if (kmax < 1) kmax = 1;
+    if (kmax > 10) kmax = 10;
     const int page = c64 ? 18 : 17;
-    const int r = n - kTileBits, P1 = (r + 9) / 10;
+    const int r = n - kTileBits, P1 = (r + kmax - 1) / kmax;
     std::vector<int> k(P1 + 1), x(P1 + 1, 0), cap(P1 + 1);
     k[0] = kTileBits;
     for (int i = 0; i < P1; ++i) k[i + 1] = r / P1 + (i < r % P1 ? 1 : 0);
@@ -114,7 +116,7 @@ std::vector<PassPlan> plan_passes(int n, bool c64)
         out[i].target_bits = tg;
         out[i].tile_bits = tg | low_mask(kTileBits - k[i]);
     }
-    if (!plan_ok(n, out)) out = plan_simple(n);
+    if (!plan_ok(n, out)) out = plan_simple(n, kmax);
     return out;
 }
 

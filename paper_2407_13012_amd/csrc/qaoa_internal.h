@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
 #include <vector>
 
 namespace qk {
@@ -57,7 +58,8 @@ struct Geometry {
 // exactly one pass; the first pass holds bits [0, 12 - x) plus x high bits.
 // Qubits whose stride crosses a 2 MiB page are spread evenly over the passes
 // so that no tile touches more than a few dozen pages.
-std::vector<PassPlan> plan_passes(int n, bool c64);
+// kmax bounds the qubits rotated by each pass after the first (at most 10).
+std::vector<PassPlan> plan_passes(int n, bool c64, int kmax = 10);
 // Kernel geometry of a plan entry; returns false if it needs more runs than supported.
 bool make_geometry(int n, const PassPlan &pp, Geometry *g);
 
@@ -114,5 +116,9 @@ hipError_t launch_exclusive_scan(const double *in, uint64_t count, double *out, 
 hipError_t launch_shots(bool c64, const void *psi, const void *C, int n, int sbits,
                         const double *pre, uint64_t nsub, int64_t shots, uint64_t seed,
                         uint64_t *z, double *cost, hipStream_t s);
+
+// Message reported by qaoa_last_error_message (thread-local, shared by all calls).
+void set_error_message(const std::string &m);
+std::string error_message();
 
 }  // namespace qk

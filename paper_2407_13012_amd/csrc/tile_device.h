@@ -1,0 +1,556 @@
+// Device-side building blocks of the tiled pass, shared by the per-pass
+// kernels (kernels.hip) and the batched engine (batch.hip).  Included by each
+// translation unit; everything here has internal linkage.
+#pragma once
+#include "qaoa_internal.h"
+
+#include <math.h>
+
+namespace qk {
+namespace {
+
+template <typename R>
+struct Tr;
+template <>
+struct Tr<double> {
+    using V = double2;
+    using CT = double;
+};
+template <>
+struct Tr<float> {
+    using V = float2;
+    using CT = float;
+};
+
+// Streaming accesses: with long contiguous runs every line is used once per
+// pass, so loads and stores may carry the nontemporal hint.  (The builtins take
+// clang vector types; values are kept in HIP vector types, which the compiler
+// register-allocates far more tightly.)
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ldnt(const double2 *p)
+{
+    const d2v t = __builtin_nontemporal_load((const d2v *)p);
+    return make_double2(t.x, t.y);
+}
+__device__ __forceinline__ float2 ldnt(const float2 *p)
+{
+    const f2v t = __builtin_nontemporal_load((const f2v *)p);
+    return make_float2(t.x, t.y);
+}
+__device__ __forceinline__ double ldnt(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ldnt(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void stnt(double2 v, double2 *p)
+{
+    d2v t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, (d2v *)p);
+}
+__device__ __forceinline__ void stnt(float2 v, float2 *p)
+{
+    f2v t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, (f2v *)p);
+}
+
+// ------------------------------------------------------------ tile geometry
+
+// LDS slot of tile element e: one padding slot after every 16 elements.  In all
+// three arrangements any 16 consecutive lanes then hit distinct 16 B bank
+// groups, and the slot is additive over the thread part and the register part
+// of e, so every access is one base register plus an immediate offset.
+constexpr int kLdsSlots = kTile + kTile / 16;
+__host__ __device__ __forceinline__ constexpr uint32_t lds_slot(uint32_t e) { return e + (e >> 4); }
+
+template <int ARR>
+__host__ __device__ __forceinline__ constexpr uint32_t elem(uint32_t lane, uint32_t wave,
+                                                            uint32_t r)
+{
+    return ARR == 0   ? (lane | (r << 6) | (wave << 10))
+           : ARR == 1 ? (r | (lane << 4) | (wave << 10))
+                      : ((lane & 15u) | ((r & 3u) << 4) | ((lane >> 4) << 6) | (wave << 8) |
+                         ((r >> 2) << 10));
+}
+
+// Tile bit held by register-index bit q in arrangement ARR.
+template <int ARR>
+__host__ __device__ constexpr uint32_t regbit(int q)
+{
+    return ARR == 0 ? 6 + q : (ARR == 1 ? q : (q < 2 ? 4 + q : 8 + q));
+}
+
+// Tile-local index -> offset of the amplitude from the tile base.
+__device__ __forceinline__ uint64_t dep(uint32_t e, const Geometry &g)
+{
+    uint64_t o = 0;
+#pragma unroll
+    for (int r = 0; r < kTileRuns; ++r)
+        o |= (uint64_t)((e >> g.t_src[r]) & ((1u << g.t_len[r]) - 1u)) << g.t_dst[r];
+    return o;
+}
+
+// Tile index -> base index of the tile (the tile bits set to zero).
+__device__ __forceinline__ uint64_t tile_base(uint64_t t, const Geometry &g)
+{
+    uint64_t o = 0;
+#pragma unroll
+    for (int r = 0; r < kFreeRuns; ++r)
+        o |= ((t >> g.f_src[r]) & ((1ull << g.f_len[r]) - 1ull)) << g.f_dst[r];
+    return o;
+}
+
+// ------------------------------------------------------------ arithmetic
+
+template <typename V, typename R>
+__device__ __forceinline__ V cmul(V v, R c, R s)
+{
+    V o;
+    o.x = v.x * c - v.y * s;
+    o.y = v.x * s + v.y * c;
+    return o;
+}
+
+template <typename V, typename R>
+__device__ __forceinline__ V vscale(V v, R f)
+{
+    V o;
+    o.x = v.x * f;
+    o.y = v.y * f;
+    return o;
+}
+
+template <typename V>
+__device__ __forceinline__ double norm2(V v)
+{
+    return (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+}
+
+// Im(conj(u) v)
+template <typename V>
+__device__ __forceinline__ double imcx(V u, V v)
+{
+    return (double)u.x * (double)v.y - (double)u.y * (double)v.x;
+}
+
+// sin and cos of x in fp64.  Cody-Waite reduction x = k pi/2 + r with pi/2
+// split into two 33-bit parts and a remainder (k pi/2 is exact for |k| < 2^20),
+// then the Taylor series of sin (to r^17) and cos (to r^18) on |r| <= pi/4,
+// whose truncation error is below 1e-19.  Larger arguments use the library.
+__device__ __forceinline__ void sincos_cw(double x, double &s, double &c)
+{
+    if (!(fabs(x) < 1.0e6)) {
+        sincos(x, &s, &c);
+        return;
+    }
+    const double k = rint(x * 0x1.45f306dc9c883p-1);  // 2/pi
+    double r = fma(-k, 0x1.921fb54400000p+0, x);
+    r = fma(-k, 0x1.0b4611a600000p-34, r);
+    r = fma(-k, 0x1.3198a2e037073p-69, r);
+    const double r2 = r * r;
+    double ps = 2.8114572543455206e-15;  //  1/17!
+    ps = fma(ps, r2, -7.647163731819816e-13);   // -1/15!
+    ps = fma(ps, r2, 1.6059043836821613e-10);   //  1/13!
+    ps = fma(ps, r2, -2.505210838544172e-08);   // -1/11!
+    ps = fma(ps, r2, 2.7557319223985893e-06);   //  1/9!
+    ps = fma(ps, r2, -0.0001984126984126984);   // -1/7!
+    ps = fma(ps, r2, 0.008333333333333333);     //  1/5!
+    ps = fma(ps, r2, -0.16666666666666666);     // -1/3!
+    const double sr = fma(ps * r2, r, r);
+    double pc = -1.5619206968586225e-16;  // -1/18!
+    pc = fma(pc, r2, 4.779477332387385e-14);    //  1/16!
+    pc = fma(pc, r2, -1.1470745597729725e-11);  // -1/14!
+    pc = fma(pc, r2, 2.08767569878681e-09);     //  1/12!
+    pc = fma(pc, r2, -2.755731922398589e-07);   // -1/10!
+    pc = fma(pc, r2, 2.48015873015873e-05);     //  1/8!
+    pc = fma(pc, r2, -0.001388888888888889);    // -1/6!
+    pc = fma(pc, r2, 0.041666666666666664);     //  1/4!
+    pc = fma(pc, r2, -0.5);                     // -1/2!
+    const double cr = fma(pc, r2, 1.0);
+    const int q = (int)(((long long)k) & 3);
+    // x = k pi/2 + r: rotate (cos r, sin r) by q quarter turns
+    const double s0 = (q & 1) ? cr : sr, c0 = (q & 1) ? sr : cr;
+    s = (q & 2) ? -s0 : s0;
+    c = ((q + 1) & 2) ? -c0 : c0;
+}
+
+// cos / sin of g * C.  complex128: fp64.  complex64: the product is formed and
+// reduced modulo 2 pi in fp64, then an fp32 sincos is taken.
+__device__ __forceinline__ void phase_cs(double g, double cval, double &c, double &s)
+{
+    sincos_cw(g * cval, s, c);
+}
+__device__ __forceinline__ void phase_cs(double g, float cval, float &c, float &s)
+{
+    const double th = g * (double)cval;
+    const double k = rint(th * 0.15915494309189535);
+    double r = fma(-k, 6.283185307179586, th);
+    r = fma(-k, 2.4492935982947064e-16, r);
+    sincosf((float)r, &s, &c);
+}
+
+// Factored rotation exp(-i b X) / f on the pair (a, b'):
+//   tan mode (TM):  a <- a - i m b',     b' <- b' - i m a
+//   cot mode:       a <- m a - i b',     b' <- m b' - i a
+// (same formula for the inverse rotation with its own m); one FMA per component.
+template <bool TM, typename V, typename R>
+__device__ __forceinline__ void bfly(V &a, V &b, R m)
+{
+    const R ax = a.x, ay = a.y, bx = b.x, by = b.y;
+    if constexpr (TM) {
+        a.x = fma(m, by, ax);
+        a.y = fma(-m, bx, ay);
+        b.x = fma(m, ay, bx);
+        b.y = fma(-m, ax, by);
+    } else {
+        a.x = fma(m, ax, by);
+        a.y = fma(m, ay, -bx);
+        b.x = fma(m, bx, ay);
+        b.y = fma(m, by, -ax);
+    }
+}
+
+template <int ARR, bool TM, typename V, typename R>
+__device__ __forceinline__ void mix_stage(V (&v)[16], R m, uint32_t tmask)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if ((tmask >> regbit<ARR>(q)) & 1u) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (!(r & (1 << q))) bfly<TM>(v[r], v[r | (1 << q)], m);
+        }
+    }
+}
+
+// Adjoint stage: for each target bit, add Im<lam|X_j|phi> over the register
+// pairs (weighted by sig2, the squared factor both vectors still miss), then
+// apply the factored inverse rotation to both.
+template <int ARR, bool TM, typename V, typename R>
+__device__ __forceinline__ void adj_stage(V (&f)[16], V (&l)[16], R m, uint32_t tmask,
+                                          double &sig2, double f2, double &accB)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if ((tmask >> regbit<ARR>(q)) & 1u) {
+            double ps = 0.0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (!(r & (1 << q))) {
+                    const int r1 = r | (1 << q);
+                    ps += imcx(l[r], f[r1]) + imcx(l[r1], f[r]);
+                }
+            accB = fma(sig2, ps, accB);
+            sig2 *= f2;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (!(r & (1 << q))) {
+                    bfly<TM>(l[r], l[r | (1 << q)], m);
+                    bfly<TM>(f[r], f[r | (1 << q)], m);
+                }
+        }
+    }
+}
+
+// Sum over the target bits owned by arrangement ARR of Im<lam|X_j|phi> on the
+// register pairs, times w (the product of the factors both vectors miss).
+template <int ARR, typename V>
+__device__ __forceinline__ void beta_terms(const V (&f)[16], const V (&l)[16], uint32_t tmask,
+                                           double w, double &accB)
+{
+    double ps = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if ((tmask >> regbit<ARR>(q)) & 1u) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (!(r & (1 << q))) {
+                    const int r1 = r | (1 << q);
+                    ps += imcx(l[r], f[r1]) + imcx(l[r1], f[r]);
+                }
+        }
+    }
+    accB = fma(w, ps, accB);
+}
+
+__host__ __device__ __forceinline__ int popc(uint32_t x) { return __builtin_popcount(x); }
+
+__device__ __forceinline__ double upow(double f, int k)
+{
+    double r = 1.0;
+    for (int i = 0; i < k; ++i) r *= f;
+    return r;
+}
+
+template <int FROM, int TO, typename V>
+__device__ __forceinline__ void xpose(V (&v)[16], V *lds, uint32_t lane, uint32_t wave)
+{
+    V *wr = lds + lds_slot(elem<FROM>(lane, wave, 0));
+    V *rd = lds + lds_slot(elem<TO>(lane, wave, 0));
+#pragma unroll
+    for (int r = 0; r < 16; ++r) wr[lds_slot(elem<FROM>(0, 0, r))] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = rd[lds_slot(elem<TO>(0, 0, r))];
+    __syncthreads();
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+// Sum of `x` over a 256-thread block in fixed order; valid in thread 0.
+// `scratch` must hold 4 doubles and not be in use by other threads.
+__device__ __forceinline__ double block_sum(double x, double *scratch)
+{
+    x = wave_sum(x);
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    if (lane == 0) scratch[wave] = x;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = ((scratch[0] + scratch[1]) + scratch[2]) + scratch[3];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld(const T *p, bool stream)
+{
+    return stream ? ldnt(p) : *p;
+}
+template <typename T>
+__device__ __forceinline__ void st(T v, T *p, bool stream)
+{
+    if (stream) stnt(v, p);
+    else *p = v;
+}
+
+// ------------------------------------------------------------ pass kernel
+
+// One pass over tile t: load, [phase], rotations, [E / adjoint terms / phase
+// undo], store.  The workgroup's sums of the E, <lam|X|phi> and <lam|C|phi>
+// terms are returned in sums[0..2] (valid in thread 0; zero when not taken).
+template <typename R, int MODE, bool TM>
+__device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typename Tr<R>::V *lds,
+                                          double (&sums)[3])
+{
+    using V = typename Tr<R>::V;
+    using CT = typename Tr<R>::CT;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const Geometry &g = a.geo;
+    const uint64_t base = tile_base(t, g);
+    const bool full = g.tbits == (uint32_t)kTileBits;
+    const uint32_t lim = 1u << g.tbits;
+    const uint32_t tmask = g.tmask;
+    const bool strm = (a.flags & kStream) != 0;
+    V *psi = (V *)a.psi;
+    V *lam = (V *)a.lam;
+    const CT *cost = (const CT *)a.cost;
+
+    // Global index of register r in arrangement A / C: a per-thread part plus a
+    // part that depends on r only (the same for every thread of the grid).
+    const uint64_t thrA = base | dep(elem<0>(lane, wave, 0), g);
+    const uint64_t thrC = base | dep(elem<2>(lane, wave, 0), g);
+#define ZA(r) (thrA | dep(elem<0>(0, 0, (r)), g))
+#define ZC(r) (thrC | dep(elem<2>(0, 0, (r)), g))
+#define VA(r) (full || elem<0>(lane, wave, (r)) < lim)
+#define VC(r) (full || elem<2>(lane, wave, (r)) < lim)
+
+    double accE = 0.0, accB = 0.0, accG = 0.0;
+    const V zero = {(R)0, (R)0};
+
+    // All global loads of the pass are issued up front (cost entries first);
+    // loads placed after the arithmetic were found to serialise with it.
+    constexpr bool TURN = MODE == kTurn || MODE == kTurnPhase;
+    // which optional steps this launch performs (compile-time where the mode decides)
+    const bool phaseIn = MODE == kTurnPhase || (MODE == kFwd && (a.flags & kPhaseIn));
+    const bool phaseOut = MODE == kTurnPhase || (MODE == kBwd && (a.flags & kPhaseOut));
+    const bool costC = TURN || phaseOut || (MODE == kFwd && (a.flags & kEOut));
+    CT cin[16], cv[16];
+    if (phaseIn) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) cin[r] = VA(r) ? ld(&cost[ZA(r)], strm) : (CT)0;
+    }
+    if (costC) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) cv[r] = VC(r) ? ld(&cost[ZC(r)], strm) : (CT)0;
+    }
+
+    if constexpr (MODE == kFwd || TURN) {
+        V v[16];
+        if (a.flags & kInit) {
+            const V a0 = {(R)a.amp0, (R)0};
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = VA(r) ? a0 : zero;
+        } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = VA(r) ? ld(&psi[ZA(r)], strm) : zero;
+        }
+        if (phaseIn) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (VA(r)) {
+                    R c, s;
+                    phase_cs(-a.gamma_in, cin[r], c, s);
+                    v[r] = cmul(v[r], c, s);
+                }
+        }
+        const R mf = (R)a.mul_f;
+        mix_stage<0, TM>(v, mf, tmask);
+        xpose<0, 1>(v, lds, lane, wave);
+        mix_stage<1, TM>(v, mf, tmask);
+        xpose<1, 2>(v, lds, lane, wave);
+        mix_stage<2, TM>(v, mf, tmask);
+        const R sf = (R)a.scl_f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = vscale(v[r], sf);
+
+        if constexpr (MODE == kFwd) {
+            if (a.flags & kEOut) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) accE += (double)cv[r] * norm2(v[r]);
+            }
+            if (!(a.flags & kNoStore)) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    if (VC(r)) st(v[r], &psi[ZC(r)], strm);
+            }
+        } else {
+            // v is the final state phi on this tile: E, lam = C phi, then undo the
+            // group on both, visiting the register arrangements C, B, A; lam is
+            // stored from A (from C when the phase is undone too).
+            V l[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                accE += (double)cv[r] * norm2(v[r]);
+                l[r] = vscale(v[r], (R)cv[r]);
+            }
+            // Materialise the E sum here: left to the compiler it is sunk to its use
+            // after the backward stages, keeping phi and C live (register spills).
+            asm volatile("" : "+v"(accE));
+            const R mb = (R)a.mul_b;
+            const R sb = (R)a.scl_b;
+            if constexpr (MODE == kTurn) {
+                // <lam|X_j|phi> of an arrangement's bits is taken at its entry, where
+                // both vectors sit at the same point.  Arrangement C: the final point.
+                // Then undo C's rotations on lam only; phi before stage C is still in
+                // LDS from the forward B->C transpose, so it is re-read, not recomputed.
+                const int kA = popc(tmask & (15u << 6)), kB = popc(tmask & 15u);
+                const int kC = popc(tmask & ((3u << 4) | (3u << 10)));
+                const double ff = a.fac_f, fb = a.fac_b;
+                beta_terms<2>(v, l, tmask, 1.0, accB);
+                mix_stage<2, TM>(l, mb, tmask);
+                {
+                    const V *rd = lds + lds_slot(elem<1>(lane, wave, 0));
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) v[r] = rd[lds_slot(elem<1>(0, 0, r))];
+                    __syncthreads();
+                }
+                xpose<2, 1>(l, lds, lane, wave);
+                // lam misses fb^kC, phi (forward stages A, B) misses ff^(kA+kB)
+                beta_terms<1>(v, l, tmask, upow(fb, kC) * upow(ff, kA + kB), accB);
+                mix_stage<1, TM>(l, mb, tmask);
+                mix_stage<1, TM>(v, mb, tmask);
+                xpose<1, 0>(v, lds, lane, wave);
+                xpose<1, 0>(l, lds, lane, wave);
+                beta_terms<0>(v, l, tmask, upow(fb, kC + 2 * kB) * upow(ff, kA + kB), accB);
+                mix_stage<0, TM>(l, mb, tmask);
+                if (!(a.flags & kNoStore)) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        if (VA(r)) st(vscale(l[r], sb), &lam[ZA(r)], strm);
+                }
+            } else {
+            const double f2 = a.fac_b * a.fac_b;
+            double sig2 = 1.0;
+            adj_stage<2, TM>(v, l, mb, tmask, sig2, f2, accB);
+            xpose<2, 1>(v, lds, lane, wave);
+            xpose<2, 1>(l, lds, lane, wave);
+            adj_stage<1, TM>(v, l, mb, tmask, sig2, f2, accB);
+            xpose<1, 0>(v, lds, lane, wave);
+            xpose<1, 0>(l, lds, lane, wave);
+            adj_stage<0, TM>(v, l, mb, tmask, sig2, f2, accB);
+                xpose<0, 2>(l, lds, lane, wave);
+                xpose<0, 2>(v, lds, lane, wave);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    l[r] = vscale(l[r], sb);
+                    if (VC(r)) {
+                        accG += (double)cv[r] * imcx(l[r], vscale(v[r], sb));
+                        R c, s;
+                        phase_cs(a.gamma_out, cv[r], c, s);
+                        l[r] = cmul(l[r], c, s);
+                    }
+                }
+                if (!(a.flags & kNoStore)) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        if (VC(r)) st(l[r], &lam[ZC(r)], strm);
+                }
+            }
+        }
+    } else {
+        V f[16], l[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const bool ok = VA(r);
+            f[r] = ok ? ld(&psi[ZA(r)], strm) : zero;
+            l[r] = ok ? ld(&lam[ZA(r)], strm) : zero;
+        }
+        const R mb = (R)a.mul_b;
+        const double f2 = a.fac_b * a.fac_b;
+        double sig2 = 1.0;
+        adj_stage<0, TM>(f, l, mb, tmask, sig2, f2, accB);
+        xpose<0, 1>(f, lds, lane, wave);
+        xpose<0, 1>(l, lds, lane, wave);
+        adj_stage<1, TM>(f, l, mb, tmask, sig2, f2, accB);
+        xpose<1, 2>(f, lds, lane, wave);
+        xpose<1, 2>(l, lds, lane, wave);
+        adj_stage<2, TM>(f, l, mb, tmask, sig2, f2, accB);
+        const R sb = (R)a.scl_b;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            f[r] = vscale(f[r], sb);
+            l[r] = vscale(l[r], sb);
+        }
+        if (phaseOut) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (VC(r)) {
+                    accG += (double)cv[r] * imcx(l[r], f[r]);
+                    R c, s;
+                    phase_cs(a.gamma_out, cv[r], c, s);
+                    f[r] = cmul(f[r], c, s);
+                    l[r] = cmul(l[r], c, s);
+                }
+        }
+        if (!(a.flags & kNoStore)) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (VC(r)) {
+                    st(f[r], &psi[ZC(r)], strm);
+                    st(l[r], &lam[ZC(r)], strm);
+                }
+        }
+    }
+#undef ZA
+#undef ZC
+#undef VA
+#undef VC
+
+    // Fixed-order block reductions.
+    double *red = (double *)lds;  // every LDS read above completed before the last barrier
+    const bool wantE = TURN || (MODE == kFwd && (a.flags & kEOut));
+    const bool wantB = MODE != kFwd;
+    const bool wantG = phaseOut;
+    sums[0] = wantE ? block_sum(accE, red) : 0.0;
+    sums[1] = wantB ? block_sum(accB, red) : 0.0;
+    sums[2] = wantG ? block_sum(accG, red) : 0.0;
+}
+
+}  // namespace
+}  // namespace qk

@@ -182,3 +182,63 @@ def test_pass_plan_rejects():
         qaoa_pass_plan(0)
     with pytest.raises(QaoaError):
         qaoa_pass_plan(41)
+
+
+# ---------------------------------------------------------------- batched engine (validation only)
+
+def _batch_create(lib, n, off, edges, w=None, p=2, opt=None, out=True):
+    import paper_2407_13012_amd as pkg
+    nn = np.ascontiguousarray(n, dtype=np.int32)
+    oo = np.ascontiguousarray(off, dtype=np.int64)
+    ee = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    ww = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    h = ctypes.c_void_p()
+    return lib.qaoa_batch_create(len(nn), nn.ctypes.data if nn.size else None, oo.ctypes.data,
+                                 ee.ctypes.data if ee.size else None,
+                                 None if ww is None else ww.ctypes.data, p,
+                                 ctypes.byref(opt) if opt is not None else None,
+                                 ctypes.byref(h) if out else None)
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=[], off=[0], edges=[]),                                  # empty batch
+    dict(n=[4], off=[0, 1], edges=[[0, 1]], p=0),                   # p too small
+    dict(n=[4], off=[0, 1], edges=[[0, 1]], p=17),                  # p too large
+    dict(n=[1], off=[0, 0], edges=[]),                              # n too small
+    dict(n=[25], off=[0, 1], edges=[[0, 1]]),                       # n too large
+    dict(n=[4], off=[1, 1], edges=[[0, 1]]),                        # offsets must start at 0
+    dict(n=[4, 4], off=[0, 2, 1], edges=[[0, 1], [1, 2]]),          # decreasing offsets
+    dict(n=[4], off=[0, 1], edges=[[0, 4]]),                        # vertex out of range
+    dict(n=[4], off=[0, 1], edges=[[2, 2]]),                        # self-loop
+    dict(n=[4], off=[0, 1], edges=[[0, 1]], w=[float("nan")]),      # non-finite weight
+    dict(n=[4], off=[0, 1], edges=[[0, 1]], out=False),             # NULL out
+])
+def test_batch_create_rejects(lib, case):
+    assert _batch_create(lib, **case) == 1
+    lib.qaoa_last_error_message.restype = ctypes.c_char_p
+    assert lib.qaoa_last_error_message() != b""
+
+
+@pytest.mark.parametrize("field,value", [("steps", -1), ("lr", 0.0), ("beta1", 1.0), ("beta2", -0.1),
+                                         ("eps", 0.0), ("workgroups", -2), ("max_group", 0),
+                                         ("max_group", 11)])
+def test_batch_create_rejects_options(lib, field, value):
+    from paper_2407_13012_amd import batch_options
+    opt = batch_options()
+    setattr(opt, field, value)
+    assert _batch_create(lib, [4], [0, 1], [[0, 1]], opt=opt) == 1
+    opt = batch_options(group_by_n={5: 11})
+    assert _batch_create(lib, [4], [0, 1], [[0, 1]], opt=opt) == 1
+
+
+def test_batch_run_rejects(lib):
+    g = np.zeros(2)
+    assert lib.qaoa_batch_run(None, g.ctypes.data, g.ctypes.data, None, None, None, None) == 1
+    assert lib.qaoa_batch_destroy(None) == 0
+
+
+def test_batch_valid_create_without_gpu_reports_device_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert _batch_create(lib, [4, 6], [0, 1, 3], [[0, 1], [0, 5], [2, 3]]) == 3

@@ -1,0 +1,175 @@
+"""GPU parity of the batched engine (qaoa_batch_*) against the CPU oracle.
+
+Each instance's Adam trajectory is compared with oracle.adam_qaoa on the same
+graph, start angles and hyper-parameters: angles and expectations after a few
+steps within 1e-8 (gradients agree to ~1e-12, and a few Adam steps amplify
+that by at most lr / sqrt(v)); the start expectation within 1e-10 * sum|w|.
+Batches mix sizes across the pass structure (n <= 12: one tile; 13..20: a low
+and a high pass; ragged last tile groups) and are processed by fewer workgroups
+than instances, so the queue hands several instances to each workgroup.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import qaoa_inputs as qi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    from paper_2407_13012_amd import load_library
+    load_library()
+
+
+def family(sizes, seed=0, weights="uniform"):
+    out = []
+    for k, n in enumerate(sizes):
+        if weights == "unit":
+            out.append(qi.erdos_renyi(n, 0.5, seed=[seed, k]))
+        else:
+            out.append(qi.erdos_renyi(n, 0.5, seed=[seed, k], weights="uniform", wlow=-1, whigh=1))
+    return out
+
+
+def start_angles(graphs, p, seed=1):
+    rng = np.random.default_rng(seed)
+    g0 = np.stack([qi.linear_ramp(p)[0] for _ in graphs]) + rng.normal(0, 0.05, (len(graphs), p))
+    b0 = np.stack([qi.linear_ramp(p)[1] for _ in graphs]) + rng.normal(0, 0.05, (len(graphs), p))
+    return g0, b0
+
+
+def scale_of(g):
+    s = float(np.abs(g.weight_array()).sum())
+    return 1.0 / s if s > 0 else 1.0
+
+
+def run_batch(graphs, p, g0, b0, **opt):
+    from paper_2407_13012_amd import QaoaBatch
+    with QaoaBatch(graphs, p, **opt) as b:
+        return b.run(g0, b0)
+
+
+def oracle_adam(g, gamma, beta, steps, **kw):
+    C = oracle.cost_of(g)
+    return oracle.adam_qaoa(g.n, C, gamma, beta, steps, scale=scale_of(g), **kw)
+
+
+def check_against_oracle(graphs, p, g0, b0, res, steps, atol=1e-8, **kw):
+    gam, bet, e0, e1 = res
+    for i, g in enumerate(graphs):
+        og, ob, oe0, oe1 = oracle_adam(g, g0[i], b0[i], steps, **kw)
+        tolE = 1e-10 * max(1.0, float(np.abs(g.weight_array()).sum()))
+        assert abs(e0[i] - oe0) <= tolE, (i, g.n, e0[i], oe0)
+        np.testing.assert_allclose(gam[i], og, rtol=0, atol=atol, err_msg=f"instance {i} n={g.n}")
+        np.testing.assert_allclose(bet[i], ob, rtol=0, atol=atol, err_msg=f"instance {i} n={g.n}")
+        assert abs(e1[i] - oe1) <= max(tolE, atol * 10), (i, g.n, e1[i], oe1)
+
+
+def test_batch_zero_steps_is_expectation():
+    sizes = [2, 3, 5, 9, 12, 13, 16]
+    graphs = family(sizes, seed=3)
+    g0, b0 = start_angles(graphs, 3)
+    gam, bet, e0, e1 = run_batch(graphs, 3, g0, b0, steps=0, workgroups=3)
+    np.testing.assert_array_equal(gam, g0)
+    np.testing.assert_array_equal(bet, b0)
+    for i, g in enumerate(graphs):
+        C = oracle.cost_of(g)
+        E = oracle.expectation(g.n, C, oracle.state(g.n, C, g0[i], b0[i]))
+        tol = 1e-10 * max(1.0, float(np.abs(g.weight_array()).sum()))
+        assert abs(e0[i] - E) <= tol and abs(e1[i] - E) <= tol, (g.n, e0[i], e1[i], E)
+
+
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_batch_adam_matches_oracle(p):
+    sizes = [10, 4, 12, 13, 7, 11, 14, 6, 15]
+    graphs = family(sizes, seed=10 + p)
+    g0, b0 = start_angles(graphs, p, seed=p)
+    res = run_batch(graphs, p, g0, b0, steps=4, workgroups=4)
+    check_against_oracle(graphs, p, g0, b0, res, steps=4)
+
+
+def test_batch_unit_weights_and_hyperparameters():
+    graphs = family([5, 8, 13], seed=21, weights="unit")
+    g0, b0 = start_angles(graphs, 2, seed=5)
+    kw = dict(lr=0.02, beta1=0.8, beta2=0.99, eps=1e-6)
+    res = run_batch(graphs, 2, g0, b0, steps=5, workgroups=2, **kw)
+    check_against_oracle(graphs, 2, g0, b0, res, steps=5, lr=0.02, beta1=0.8, beta2=0.99, eps=1e-6)
+
+
+def test_batch_edgeless_instance_keeps_angles():
+    """C = 0: every gradient is zero, so Adam's steps are 0 / (0 + eps) = 0."""
+    graphs = [qi.MaxCut(n=6, edges=np.zeros((0, 2), np.int32), weights=None)] + family([7], seed=2)
+    g0, b0 = start_angles(graphs, 2)
+    gam, bet, e0, e1 = run_batch(graphs, 2, g0, b0, steps=3)
+    np.testing.assert_array_equal(gam[0], g0[0])
+    np.testing.assert_array_equal(bet[0], b0[0])
+    assert e0[0] == 0.0 and e1[0] == 0.0
+
+
+def test_batch_graph_replay_matches_eager_and_repeats():
+    """The captured graph (reset kernel + engine) replayed twice and an eager
+    launch give bitwise identical results: each instance is handled by one
+    workgroup whose arithmetic does not depend on which workgroup it is."""
+    from paper_2407_13012_amd import QaoaBatch
+    graphs = family([11, 14, 9, 13, 12, 6], seed=31)
+    g0, b0 = start_angles(graphs, 3, seed=9)
+    with QaoaBatch(graphs, 3, steps=3, workgroups=3, use_graph=True) as b:
+        r1 = b.run(g0, b0)
+        r2 = b.run(g0, b0)
+        r3 = b.run(g0 + 0.01, b0)
+    r4 = run_batch(graphs, 3, g0, b0, steps=3, workgroups=5, use_graph=False)
+    for a, c in zip(r1, r2):
+        np.testing.assert_array_equal(a, c)
+    for a, c in zip(r1, r4):
+        np.testing.assert_array_equal(a, c)
+    assert not np.array_equal(r3[0], r1[0])
+
+
+@pytest.mark.parametrize("kmax", [4, 7])
+def test_batch_pass_depth_does_not_change_results(kmax):
+    """A smaller fusion depth (more, narrower mixer passes) changes only rounding."""
+    graphs = family([13, 16, 18], seed=41)
+    g0, b0 = start_angles(graphs, 2, seed=4)
+    ref = run_batch(graphs, 2, g0, b0, steps=3, workgroups=2)
+    alt = run_batch(graphs, 2, g0, b0, steps=3, workgroups=2, max_group=kmax,
+                    group_by_n={16: max(1, kmax - 2)})
+    for a, c in zip(ref, alt):
+        np.testing.assert_allclose(a, c, rtol=0, atol=1e-9)
+
+
+def test_batch_single_workgroup_and_more_workgroups_than_instances():
+    graphs = family([9, 12, 5], seed=51)
+    g0, b0 = start_angles(graphs, 2, seed=6)
+    r1 = run_batch(graphs, 2, g0, b0, steps=2, workgroups=1)
+    r2 = run_batch(graphs, 2, g0, b0, steps=2, workgroups=64)
+    for a, c in zip(r1, r2):
+        np.testing.assert_array_equal(a, c)
+    check_against_oracle(graphs, 2, g0, b0, r1, steps=2)
+
+
+def test_batch_family_sampled_full_run():
+    """The 4096-graph family's size mix at reduced count: 256 graphs of
+    n ~ U{10..20}, p = 4, 100 Adam steps from the linear ramp.  Instances with
+    n <= 13 are checked against the oracle's 100-step trajectory; all
+    instance but a few must improve E."""
+    graphs = qi.batched_family(256)
+    p = 4
+    g0 = np.tile(qi.linear_ramp(p)[0], (len(graphs), 1))
+    b0 = np.tile(qi.linear_ramp(p)[1], (len(graphs), 1))
+    gam, bet, e0, e1 = run_batch(graphs, p, g0, b0, steps=100)
+    assert np.all(np.isfinite(gam)) and np.all(np.isfinite(bet))
+    improved = np.mean(e1 > e0)
+    assert improved >= 0.95, improved
+    picked = [i for i, g in enumerate(graphs) if g.n <= 13][:6]
+    assert picked
+    for i in picked:
+        g = graphs[i]
+        og, ob, oe0, oe1 = oracle_adam(g, g0[i], b0[i], 100)
+        np.testing.assert_allclose(gam[i], og, rtol=0, atol=1e-6, err_msg=f"n={g.n}")
+        np.testing.assert_allclose(bet[i], ob, rtol=0, atol=1e-6, err_msg=f"n={g.n}")
+        assert abs(e1[i] - oe1) <= 1e-7 * max(1.0, float(np.abs(g.weight_array()).sum()))

@@ -497,3 +497,50 @@ def test_sample_inverse_cdf_definition():
         k = int(z[s])
         assert cdf[k] > t * (1 - 1e-14)
         assert k == 0 or cdf[k - 1] <= t * (1 + 1e-14)
+
+
+# ---------------------------------------------------------------- Adam loop of the batched optimiser
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient c the bias-corrected moments are c and c^2, so
+    every step moves by lr * c / (|c| + eps)."""
+    c = np.array([0.3, -2.0, 1e-3])
+    lr, eps = 0.05, 1e-8
+    x, f0, f1 = oracle.adam_ascent(lambda x: (float(c @ x), c), np.zeros(3), 7, lr, 0.9, 0.999, eps)
+    np.testing.assert_allclose(x, 7 * lr * c / (np.abs(c) + eps), rtol=1e-12, atol=0)
+    assert f0 == 0.0 and f1 == pytest.approx(float(c @ x), abs=1e-15)
+
+
+def test_adam_matches_torch_optimizer():
+    """Ascent on f equals torch.optim.Adam's descent on -f (float64, CPU)."""
+    import torch
+    A = np.array([[2.0, 0.5, 0.0], [0.5, 1.0, -0.3], [0.0, -0.3, 0.7]])
+    b = np.array([0.2, -1.0, 0.4])
+
+    def f(x):
+        return float(-0.5 * x @ A @ x + b @ x), -A @ x + b
+
+    x0 = np.array([0.1, 0.2, -0.3])
+    x, _, _ = oracle.adam_ascent(f, x0, 25, 0.05, 0.9, 0.999, 1e-8)
+    xt = torch.tensor(x0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([xt], lr=0.05, betas=(0.9, 0.999), eps=1e-8)
+    At, bt = torch.tensor(A), torch.tensor(b)
+    for _ in range(25):
+        opt.zero_grad()
+        loss = -(-0.5 * xt @ At @ xt + bt @ xt)
+        loss.backward()
+        opt.step()
+    np.testing.assert_allclose(x, xt.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_adam_qaoa_increases_expectation_and_scales():
+    """Adam on the p=1 MaxCut expectation climbs; the objective scale does not
+    change the first step (Adam is invariant to a constant gradient scale up to eps)."""
+    g = qi.erdos_renyi(8, 0.5, seed=11, weights="uniform", wlow=-1, whigh=1)
+    C = oracle.cost_of(g)
+    gm, bt, e0, e1 = oracle.adam_qaoa(8, C, [0.2], [0.3], steps=30)
+    assert e1 > e0
+    g1, b1, _, _ = oracle.adam_qaoa(8, C, [0.2], [0.3], steps=1, scale=1.0)
+    g2, b2, _, _ = oracle.adam_qaoa(8, C, [0.2], [0.3], steps=1, scale=0.125)
+    np.testing.assert_allclose(np.r_[g1, b1], np.r_[g2, b2], rtol=0, atol=1e-7)
+    np.testing.assert_allclose(np.abs(np.r_[g1 - 0.2, b1 - 0.3]), 0.05, rtol=0, atol=1e-6)
