@@ -89,6 +89,56 @@ def time_gradients(q, gamma, beta, steps, warmup):
     return t1 - t0, prof
 
 
+def batch_bytes_per_amp(n: int, p: int, kmax: int = 10) -> float:
+    """Algorithmic bytes per amplitude of one batched-engine E+G (complex128, fp64 C):
+    p layers forward (P passes each moving psi, one also reading C), one sweep
+    forming E and lam = C psi, p layers backward (P passes moving phi and lam, one
+    also reading C), the last pass storing nothing."""
+    s, c = 16, 8
+    P = 1 if n <= 12 else 1 + -(-(n - 12) // kmax)
+    return p * P * 2 * s + p * c + (2 * s + c) + p * P * 4 * s + p * c - 2 * s
+
+
+def batch_leg(count: int, p: int, steps: int, log) -> dict:
+    """The batched engine on the n ~ U{10..20} MaxCut family: `count` graphs,
+    depth p, `steps` Adam steps each, all in one persistent launch."""
+    import numpy as np
+    import torch
+
+    import qaoa_inputs as qi
+    from paper_2407_13012_amd import QaoaBatch
+    from paper_2407_13012_amd import batch_tune as bt
+
+    graphs = qi.batched_family(count)
+    t0 = time.perf_counter()
+    choice = bt.tune(graphs, p, log=log)
+    t_tune = time.perf_counter() - t0
+    opts = bt.options_of(choice)
+    g0, b0 = bt.ramp_angles(count, p)
+    with QaoaBatch(graphs, p, steps=steps, **opts) as b:
+        b.run(g0, b0)  # warm-up: first graph launch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gam, bet, e0, e1 = b.run(g0, b0)
+        dt = time.perf_counter() - t0
+    ns = np.array([g.n for g in graphs])
+    kmax = {int(k): int(v) for k, v in choice["group_by_n"].items()}
+    amps = float(np.sum(2.0 ** ns))
+    algo = sum(batch_bytes_per_amp(int(n), p, kmax.get(int(n), 10)) * 2.0 ** n for n in ns) * steps
+    evals = count * steps
+    log(f"[bench] batch {count} graphs x {steps} steps: {dt:.2f} s ({evals / dt:.0f} E+G/s)")
+    return {
+        "graphs": count, "p": p, "adam_steps": steps, "seconds": dt,
+        "grad_evals_per_s": evals / dt,
+        "amplitude_layer_updates_per_s": amps * 2 * p * steps / dt,
+        "algorithmic_GBps": algo / dt / 1e9,
+        "mean_E_gain": float(np.mean(e1 - e0)),
+        "improved_fraction": float(np.mean(e1 > e0)),
+        "tuned": {k: choice[k] for k in ("group_by_n", "waves_per_simd", "workgroups")},
+        "tune_s": t_tune,
+    }
+
+
 def cpu_baseline(inst_fn, p_n, full_n, gamma, beta):
     import oracle
     inst = inst_fn(p_n)["instance"]
@@ -117,6 +167,9 @@ def main() -> int:
     ap.add_argument("--cpu-sample-n", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="first run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -224,6 +277,10 @@ def main() -> int:
                                        "gbs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
                                    for k, v in prof64.items()}}
         print(f"[bench] c64 {extra['c64']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+
+    if not args.no_batch:
+        extra["batch"] = batch_leg(args.batch_graphs, 4, args.batch_steps,
+                                   lambda m: print(m, file=sys.stderr, flush=True))
 
     cpu = None
     if not args.no_cpu_baseline:

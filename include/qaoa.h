@@ -271,6 +271,7 @@ typedef struct {
     int32_t workgroups; /* persistent workgroups (scratch slots); 0 = 2 per compute unit */
     int32_t max_group;  /* most qubits rotated per mixer pass after the first, 1..10 */
     int32_t use_graph;  /* nonzero: replay a captured hipGraph; 0: launch eagerly */
+    int32_t waves_per_simd; /* register budget of the engine kernel: 1 or 2 waves per SIMD (0 = 1) */
     int32_t group_by_n[QAOA_BATCH_MAX_QUBITS + 1]; /* per-n override of max_group; 0 = none */
 } qaoa_batch_options;
 
@@ -282,7 +283,7 @@ typedef struct {
  *   edges         host int32 [E][2] with vertex indices local to the instance
  *                 (0 <= u, v < n[i], u != v); E = edge_offsets[count]
  *   w             host fp64 [E], finite; NULL means unit weights
- *   opt           NULL means {100, 0.05, 0.9, 0.999, 1e-8, 0, 10, 1, {0}}
+ *   opt           NULL means {100, 0.05, 0.9, 0.999, 1e-8, 0, 10, 1, 0, {0}}
  * Allocates all device memory (instances, angles, scratch slots) on the current
  * device and its own non-blocking stream; nothing is allocated by qaoa_batch_run.
  * Errors: INVALID_ARGUMENT, OUT_OF_MEMORY (slots exceed free memory), DEVICE.

@@ -31,7 +31,7 @@ class BatchOptions(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int32), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
                 ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("workgroups", ctypes.c_int32),
                 ("max_group", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("group_by_n", ctypes.c_int32 * (BATCH_MAX_QUBITS + 1))]
+                ("waves_per_simd", ctypes.c_int32), ("group_by_n", ctypes.c_int32 * (BATCH_MAX_QUBITS + 1))]
 
 
 OBJECTIVE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -340,12 +340,12 @@ def qaoa_optimize(h, gamma, beta, max_iter=100, history=10, gtol=1e-8, ftol=0.0,
 
 
 def batch_options(steps=100, lr=0.05, beta1=0.9, beta2=0.999, eps=1e-8, workgroups=0, max_group=10,
-                  use_graph=True, group_by_n=None) -> BatchOptions:
+                  use_graph=True, waves_per_simd=1, group_by_n=None) -> BatchOptions:
     gb = (ctypes.c_int32 * (BATCH_MAX_QUBITS + 1))()
     for n, k in (group_by_n or {}).items():
         gb[int(n)] = int(k)
     return BatchOptions(int(steps), float(lr), float(beta1), float(beta2), float(eps), int(workgroups),
-                        int(max_group), 1 if use_graph else 0, gb)
+                        int(max_group), 1 if use_graph else 0, int(waves_per_simd), gb)
 
 
 def qaoa_batch_create(graphs, p: int, options: Optional[BatchOptions] = None):

@@ -201,7 +201,11 @@ __device__ __forceinline__ void wg_eval(const BatchArgs &B, int n, bool grad, co
 
 __global__ __launch_bounds__(kThreads) void k_reset(uint32_t *c) { *c = 0u; }
 
-__global__ __launch_bounds__(kThreads) void k_batch(BatchArgs B)
+// WPE = waves per SIMD the register allocation is held to: 1 leaves room for
+// every value of the tile code, 2 hides more memory latency at the cost of a
+// few spilled registers.  The tuner measures both.
+template <int WPE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_batch(BatchArgs B)
 {
     __shared__ double2 lds[kLdsSlots];
     __shared__ double th[2 * kMaxP], am[2 * kMaxP], av[2 * kMaxP], gr[2 * kMaxP + 1];
@@ -275,7 +279,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs B)
 // ------------------------------------------------------------------ C ABI
 
 struct qaoa_batch_s {
-    int count = 0, p = 0, nmax = 0, device = 0, workgroups = 0;
+    int count = 0, p = 0, nmax = 0, device = 0, workgroups = 0, wpe = 1;
     int64_t edges_total = 0;
     hipStream_t stream = nullptr;
     std::vector<void *> allocs;
@@ -317,7 +321,10 @@ qaoa_status launch_engine(qaoa_batch b)
 {
     hipLaunchKernelGGL(qk::k_reset, dim3(1), dim3(1), 0, b->stream, b->args.counter);
     BCHECK(b, hipGetLastError());
-    hipLaunchKernelGGL(qk::k_batch, dim3(b->workgroups), dim3(qk::kThreads), 0, b->stream, b->args);
+    if (b->wpe == 2)
+        hipLaunchKernelGGL(qk::k_batch<2>, dim3(b->workgroups), dim3(qk::kThreads), 0, b->stream, b->args);
+    else
+        hipLaunchKernelGGL(qk::k_batch<1>, dim3(b->workgroups), dim3(qk::kThreads), 0, b->stream, b->args);
     BCHECK(b, hipGetLastError());
     return QAOA_OK;
 }
@@ -348,7 +355,7 @@ qaoa_status qaoa_batch_create(int32_t count, const int32_t *n, const int64_t *ed
             return bfail(QAOA_ERR_INVALID_ARGUMENT, "group_by_n entries must be in [0, 10]");
     if (o.steps < 0 || !(o.lr > 0.0) || !(o.beta1 >= 0.0 && o.beta1 < 1.0) ||
         !(o.beta2 >= 0.0 && o.beta2 < 1.0) || !(o.eps > 0.0) || o.workgroups < 0 ||
-        o.max_group < 1 || o.max_group > 10)
+        o.max_group < 1 || o.max_group > 10 || o.waves_per_simd < 0 || o.waves_per_simd > 2)
         return bfail(QAOA_ERR_INVALID_ARGUMENT, "invalid options");
     if (edge_offsets[0] != 0) return bfail(QAOA_ERR_INVALID_ARGUMENT, "edge_offsets[0] must be 0");
     int nmax = 0;
@@ -380,6 +387,7 @@ qaoa_status qaoa_batch_create(int32_t count, const int32_t *n, const int64_t *ed
     b->nmax = nmax;
     b->edges_total = E;
     b->use_graph = o.use_graph != 0;
+    b->wpe = o.waves_per_simd == 2 ? 2 : 1;
     auto cleanup = [&](qaoa_status st) {
         std::string keep = qk::error_message();
         qaoa_batch_destroy(b);
@@ -391,7 +399,10 @@ qaoa_status qaoa_batch_create(int32_t count, const int32_t *n, const int64_t *ed
     if (hipGetDeviceProperties(&prop, b->device) != hipSuccess)
         return cleanup(bfail(QAOA_ERR_DEVICE, "hipGetDeviceProperties failed"));
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, qk::k_batch, qk::kThreads, 0) != hipSuccess ||
+    const hipError_t oe = b->wpe == 2
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, qk::k_batch<2>, qk::kThreads, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, qk::k_batch<1>, qk::kThreads, 0);
+    if (oe != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     b->workgroups = o.workgroups > 0 ? o.workgroups : per_cu * prop.multiProcessorCount;

@@ -340,7 +340,13 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
 {
     using V = typename Tr<R>::V;
     using CT = typename Tr<R>::CT;
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    // The thread index is passed through an empty asm so that the per-thread
+    // addresses and masks derived from it are formed inside each tile pass: a
+    // caller that loops over tiles would otherwise keep them live across the
+    // loop, next to the 16 amplitudes per thread.
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
     const Geometry &g = a.geo;
     const uint64_t base = tile_base(t, g);
     const bool full = g.tbits == (uint32_t)kTileBits;

@@ -232,3 +232,37 @@ def batched_family(count: int, base_seed: int = 3_000_000, nmin: int = 10, nmax:
         w = rng.uniform(-1.0, 1.0, edges.shape[0])
         out.append(MaxCut(n=n, edges=edges, weights=w))
     return out
+
+
+# ---------------------------------------------------------------- warm-start network inputs
+
+def mpnn_param_shapes(p: int):
+    """(name, shape) of the warm-start network's parameters in their flat order:
+    three message-passing layers (W [128][2 d], b [128], d = 32 then 128) and the
+    two-layer head (W [128][128], b [128], W [2p][128], b [2p])."""
+    out, d = [], 32
+    for l in range(3):
+        out += [(f"W{l}", (128, 2 * d)), (f"b{l}", (128,))]
+        d = 128
+    return out + [("Wh1", (128, 128)), ("bh1", (128,)), ("Wh2", (2 * p, 128)), ("bh2", (2 * p,))]
+
+
+def mpnn_init_params(p: int, seed) -> np.ndarray:
+    """Initial parameters: each (W, b) pair uniform in +-1/sqrt(row length of W);
+    the output layer scaled by 0.1 so that first predictions stay near the ramp."""
+    rng = np.random.default_rng(seed)
+    shapes = mpnn_param_shapes(p)
+    parts = []
+    for k in range(0, len(shapes), 2):
+        (wn, ws), (_, bs) = shapes[k], shapes[k + 1]
+        bound = 1.0 / math.sqrt(ws[1])
+        scale = 0.1 if wn == "Wh2" else 1.0
+        parts.append(scale * rng.uniform(-bound, bound, ws).reshape(-1))
+        parts.append(scale * rng.uniform(-bound, bound, bs))
+    return np.concatenate(parts)
+
+
+def warmstart_eval_graphs(count: int = 512, n: int = 24, base_seed: int = 4_000_000):
+    """Held-out Erdos-Renyi G(n, 0.5) graphs with weights U[-1, 1]; graph i uses seed base_seed + i."""
+    return [erdos_renyi(n, 0.5, seed=base_seed + i, weights="uniform", wlow=-1.0, whigh=1.0)
+            for i in range(count)]

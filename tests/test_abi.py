@@ -221,7 +221,8 @@ def test_batch_create_rejects(lib, case):
 
 @pytest.mark.parametrize("field,value", [("steps", -1), ("lr", 0.0), ("beta1", 1.0), ("beta2", -0.1),
                                          ("eps", 0.0), ("workgroups", -2), ("max_group", 0),
-                                         ("max_group", 11)])
+                                         ("max_group", 11), ("waves_per_simd", 3),
+                                         ("waves_per_simd", -1)])
 def test_batch_create_rejects_options(lib, field, value):
     from paper_2407_13012_amd import batch_options
     opt = batch_options()

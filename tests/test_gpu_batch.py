@@ -142,6 +142,17 @@ def test_batch_pass_depth_does_not_change_results(kmax):
         np.testing.assert_allclose(a, c, rtol=0, atol=1e-9)
 
 
+def test_batch_register_budget_variants_agree():
+    """The engine compiled for 1 and for 2 waves per SIMD runs the same arithmetic."""
+    graphs = family([14, 10, 17, 12], seed=61)
+    g0, b0 = start_angles(graphs, 3, seed=7)
+    r1 = run_batch(graphs, 3, g0, b0, steps=3, waves_per_simd=1)
+    r2 = run_batch(graphs, 3, g0, b0, steps=3, waves_per_simd=2)
+    for a, c in zip(r1, r2):
+        np.testing.assert_allclose(a, c, rtol=0, atol=1e-12)
+    check_against_oracle(graphs, 3, g0, b0, r2, steps=3)
+
+
 def test_batch_single_workgroup_and_more_workgroups_than_instances():
     graphs = family([9, 12, 5], seed=51)
     g0, b0 = start_angles(graphs, 2, seed=6)
