@@ -306,6 +306,81 @@ qaoa_status qaoa_batch_run(qaoa_batch b, const double *gamma0, const double *bet
 /* Release the batch's device memory, graph and stream.  NULL is accepted. */
 qaoa_status qaoa_batch_destroy(qaoa_batch b);
 
+/*
+ * Warm-start network: a message-passing network that predicts depth-p QAOA
+ * angles from a weighted graph, so that an optimiser (qaoa_optimize, or the
+ * batched engine) can start near good angles instead of at the linear ramp of
+ * Sec. II (QAOA background: the constant-speed schedule).
+ *
+ *   node input   x_v = (deg_v / 8, wdeg_v / 8, 1, 0 ... 0), 32 features, with
+ *                deg_v the number of incident edges and wdeg_v their weight sum
+ *   layer l      H' = ReLU([H | A H] W_l^T + b_l), l = 0, 1, 2, width 128,
+ *                A the symmetric weighted adjacency
+ *   readout      g = mean of H over the graph's nodes
+ *   head         Y = ReLU(g W_h1^T + b_h1) W_h2^T + b_h2, 2p outputs
+ *   angles       gamma_i = i/p + Y_i, beta_i = 1 - i/p + Y_{p+i}, i = 1..p
+ *   loss         mean over graphs and angles of (angle - target)^2
+ *
+ * Flat fp32 parameter vector, in this order: for l = 0, 1, 2: W_l [128][2 d_l]
+ * row-major (d_0 = 32, d_1 = d_2 = 128) then b_l [128]; W_h1 [128][128],
+ * b_h1 [128], W_h2 [2p][128], b_h2 [2p].
+ *
+ * Products run on bf16 matrix cores with fp32 accumulation; their operands
+ * (activations, messages, a bf16 copy of the fp32 master weights, and the
+ * gradients entering weight-gradient products) are rounded to bf16 (nearest
+ * even).  Everything else is fp32.  Reductions have a fixed order.
+ *
+ * Graph batches use the layout of qaoa_batch_create: n [count] (1..4096 nodes
+ * each, at most 2^24 in total), edge_offsets [count+1], edges [E][2] with local
+ * vertex indices (no self-loops), w [E] finite or NULL for unit weights.
+ */
+typedef struct qaoa_mpnn_s *qaoa_mpnn;
+
+typedef struct {
+    double lr;    /* > 0 */
+    double beta1; /* [0, 1) */
+    double beta2; /* [0, 1) */
+    double eps;   /* > 0 */
+} qaoa_mpnn_adam;
+
+/* Number of parameters of the depth-p network (1 <= p <= 16). */
+qaoa_status qaoa_mpnn_num_params(int32_t p, int64_t *count);
+
+/* Create a network with all parameters zero on the current device. */
+qaoa_status qaoa_mpnn_create(int32_t p, qaoa_mpnn *out);
+
+/* Release the network's device memory and stream.  NULL is accepted. */
+qaoa_status qaoa_mpnn_destroy(qaoa_mpnn m);
+
+/* Set the parameters from host fp32 [num_params] (finite); resets Adam's state. */
+qaoa_status qaoa_mpnn_set_params(qaoa_mpnn m, const float *theta);
+
+/* Copy the fp32 master parameters to host memory [num_params]. */
+qaoa_status qaoa_mpnn_get_params(qaoa_mpnn m, float *theta);
+
+/* Predicted angles for a batch of graphs: gamma, beta host fp64 [count][p]. */
+qaoa_status qaoa_mpnn_predict(qaoa_mpnn m, int32_t count, const int32_t *n, const int64_t *edge_offsets,
+                              const int32_t *edges, const double *w, double *gamma, double *beta);
+
+/*
+ * Loss against target angles (host fp64 [count][p] each, finite) and its
+ * gradient with respect to the parameters (host fp32 [num_params], may be
+ * NULL).  The parameters are not changed.
+ */
+qaoa_status qaoa_mpnn_loss_grad(qaoa_mpnn m, int32_t count, const int32_t *n, const int64_t *edge_offsets,
+                                const int32_t *edges, const double *w, const double *gamma_t,
+                                const double *beta_t, double *loss, float *grad);
+
+/*
+ * One training step: loss and gradient as qaoa_mpnn_loss_grad, then one Adam
+ * descent step (Kingma & Ba 2015) on the fp32 master parameters, whose bf16
+ * copy is refreshed.  opt NULL means {1e-3, 0.9, 0.999, 1e-8}.  loss (may be
+ * NULL) receives the loss before the update.
+ */
+qaoa_status qaoa_mpnn_train_step(qaoa_mpnn m, int32_t count, const int32_t *n, const int64_t *edge_offsets,
+                                 const int32_t *edges, const double *w, const double *gamma_t,
+                                 const double *beta_t, const qaoa_mpnn_adam *opt, double *loss);
+
 /* Static English description of a status code. */
 const char *qaoa_status_string(qaoa_status s);
 

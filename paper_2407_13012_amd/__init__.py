@@ -15,6 +15,16 @@ from ._binding import (  # noqa: F401
     LbfgsOptions,
     QaoaHandle,
     QaoaBatch,
+    QaoaMpnn,
+    MpnnAdam,
+    qaoa_mpnn_create,
+    qaoa_mpnn_destroy,
+    qaoa_mpnn_get_params,
+    qaoa_mpnn_loss_grad,
+    qaoa_mpnn_num_params,
+    qaoa_mpnn_predict,
+    qaoa_mpnn_set_params,
+    qaoa_mpnn_train_step,
     BatchOptions,
     batch_options,
     qaoa_batch_create,
@@ -44,4 +54,4 @@ from ._binding import (  # noqa: F401
 )
 
 __all__ = [name for name in dir() if name.startswith("qaoa_")] + [
-    "QaoaHandle", "QaoaBatch", "BatchOptions", "batch_options", "QaoaError", "QAOA_C128", "QAOA_C64", "load_library", "library_path"]
+    "QaoaHandle", "QaoaBatch", "QaoaMpnn", "MpnnAdam", "BatchOptions", "batch_options", "QaoaError", "QAOA_C128", "QAOA_C64", "load_library", "library_path"]

@@ -34,6 +34,12 @@ class BatchOptions(ctypes.Structure):
                 ("waves_per_simd", ctypes.c_int32), ("group_by_n", ctypes.c_int32 * (BATCH_MAX_QUBITS + 1))]
 
 
+class MpnnAdam(ctypes.Structure):
+    """Mirror of qaoa_mpnn_adam."""
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double)]
+
+
 OBJECTIVE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                 ctypes.c_void_p)
@@ -85,6 +91,14 @@ def load_library() -> ctypes.CDLL:
         "qaoa_batch_create": [i32, vp, vp, vp, vp, i32, ctypes.POINTER(BatchOptions), pvp],
         "qaoa_batch_run": [vp, vp, vp, vp, vp, vp, vp],
         "qaoa_batch_destroy": [vp],
+        "qaoa_mpnn_num_params": [i32, ctypes.POINTER(i64)],
+        "qaoa_mpnn_create": [i32, pvp],
+        "qaoa_mpnn_destroy": [vp],
+        "qaoa_mpnn_set_params": [vp, vp],
+        "qaoa_mpnn_get_params": [vp, vp],
+        "qaoa_mpnn_predict": [vp, i32, vp, vp, vp, vp, vp, vp],
+        "qaoa_mpnn_loss_grad": [vp, i32, vp, vp, vp, vp, vp, vp, pd, vp],
+        "qaoa_mpnn_train_step": [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(MpnnAdam), pd],
         "qaoa_profile_read": [vp, i32, ctypes.POINTER(i64), pd, pd],
     }
     for name, args in sigs.items():
@@ -348,9 +362,8 @@ def batch_options(steps=100, lr=0.05, beta1=0.9, beta2=0.999, eps=1e-8, workgrou
                         int(max_group), 1 if use_graph else 0, int(waves_per_simd), gb)
 
 
-def qaoa_batch_create(graphs, p: int, options: Optional[BatchOptions] = None):
-    """graphs: sequence of objects with .n, .edges (m, 2) and .weights (m,) or None."""
-    lib = load_library()
+def _graph_arrays(graphs):
+    """(n, edge_offsets, edges, w or None) of a graph list in the batch layout."""
     count = len(graphs)
     n = np.asarray([g.n for g in graphs], dtype=np.int32)
     m = np.asarray([np.asarray(g.edges).reshape(-1, 2).shape[0] for g in graphs], dtype=np.int64)
@@ -363,11 +376,24 @@ def qaoa_batch_create(graphs, p: int, options: Optional[BatchOptions] = None):
     w = None if unit else np.ascontiguousarray(np.concatenate(
         [np.ones(int(mi)) if g.weights is None else np.asarray(g.weights, dtype=np.float64).reshape(-1)
          for g, mi in zip(graphs, m)]) if count else np.zeros(0), dtype=np.float64)
+    return n, off, edges, w
+
+
+def _graph_ptrs(arrs):
+    n, off, edges, w = arrs
+    return (_ptr(n) if n.size else None, _ptr(off), _ptr(edges) if edges.size else None,
+            _ptr(w) if w is not None and w.size else None)
+
+
+def qaoa_batch_create(graphs, p: int, options: Optional[BatchOptions] = None):
+    """graphs: sequence of objects with .n, .edges (m, 2) and .weights (m,) or None."""
+    lib = load_library()
+    count = len(graphs)
+    arrs = _graph_arrays(graphs)
     out = ctypes.c_void_p()
     opt = ctypes.byref(options) if options is not None else None
-    _check(lib.qaoa_batch_create(count, _ptr(n) if count else None, _ptr(off),
-                                 _ptr(edges) if edges.size else None, _ptr(w) if w is not None and w.size else None,
-                                 int(p), opt, ctypes.byref(out)), "qaoa_batch_create")
+    _check(lib.qaoa_batch_create(count, *_graph_ptrs(arrs), int(p), opt, ctypes.byref(out)),
+           "qaoa_batch_create")
     return out
 
 
@@ -386,6 +412,68 @@ def qaoa_batch_run(b, gamma0, beta0):
 
 def qaoa_batch_destroy(b) -> None:
     _check(load_library().qaoa_batch_destroy(b), "qaoa_batch_destroy")
+
+
+def qaoa_mpnn_num_params(p: int) -> int:
+    c = ctypes.c_int64()
+    _check(load_library().qaoa_mpnn_num_params(int(p), ctypes.byref(c)), "qaoa_mpnn_num_params")
+    return c.value
+
+
+def qaoa_mpnn_create(p: int):
+    out = ctypes.c_void_p()
+    _check(load_library().qaoa_mpnn_create(int(p), ctypes.byref(out)), "qaoa_mpnn_create")
+    return out
+
+
+def qaoa_mpnn_destroy(m) -> None:
+    _check(load_library().qaoa_mpnn_destroy(m), "qaoa_mpnn_destroy")
+
+
+def qaoa_mpnn_set_params(m, theta) -> None:
+    t = np.ascontiguousarray(theta, dtype=np.float32)
+    _check(load_library().qaoa_mpnn_set_params(m, _ptr(t)), "qaoa_mpnn_set_params")
+
+
+def qaoa_mpnn_get_params(m, p: int) -> np.ndarray:
+    t = np.empty(qaoa_mpnn_num_params(p), dtype=np.float32)
+    _check(load_library().qaoa_mpnn_get_params(m, _ptr(t)), "qaoa_mpnn_get_params")
+    return t
+
+
+def qaoa_mpnn_predict(m, graphs, p: int):
+    arrs = _graph_arrays(graphs)
+    g = np.empty((len(graphs), p))
+    b = np.empty((len(graphs), p))
+    _check(load_library().qaoa_mpnn_predict(m, len(graphs), *_graph_ptrs(arrs), _ptr(g), _ptr(b)),
+           "qaoa_mpnn_predict")
+    return g, b
+
+
+def qaoa_mpnn_loss_grad(m, graphs, gamma_t, beta_t, p: int, want_grad: bool = True):
+    arrs = _graph_arrays(graphs)
+    gt = np.ascontiguousarray(gamma_t, dtype=np.float64)
+    bt = np.ascontiguousarray(beta_t, dtype=np.float64)
+    if gt.shape != (len(graphs), p) or bt.shape != (len(graphs), p):
+        raise ValueError("targets must have shape (count, p)")
+    loss = ctypes.c_double()
+    grad = np.empty(qaoa_mpnn_num_params(p), dtype=np.float32) if want_grad else None
+    _check(load_library().qaoa_mpnn_loss_grad(m, len(graphs), *_graph_ptrs(arrs), _ptr(gt), _ptr(bt),
+                                              ctypes.byref(loss), _ptr(grad)), "qaoa_mpnn_loss_grad")
+    return loss.value, grad
+
+
+def qaoa_mpnn_train_step(m, graphs, gamma_t, beta_t, p: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    arrs = _graph_arrays(graphs)
+    gt = np.ascontiguousarray(gamma_t, dtype=np.float64)
+    bt = np.ascontiguousarray(beta_t, dtype=np.float64)
+    if gt.shape != (len(graphs), p) or bt.shape != (len(graphs), p):
+        raise ValueError("targets must have shape (count, p)")
+    loss = ctypes.c_double()
+    opt = MpnnAdam(float(lr), float(beta1), float(beta2), float(eps))
+    _check(load_library().qaoa_mpnn_train_step(m, len(graphs), *_graph_ptrs(arrs), _ptr(gt), _ptr(bt),
+                                               ctypes.byref(opt), ctypes.byref(loss)), "qaoa_mpnn_train_step")
+    return loss.value
 
 
 PASS_KINDS = ("forward", "turn", "backward")
@@ -516,6 +604,52 @@ class QaoaBatch:
         if self._b is not None:
             qaoa_batch_destroy(self._b)
             self._b = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class QaoaMpnn:
+    """Owning wrapper of the warm-start network (qaoa_mpnn_*)."""
+
+    def __init__(self, p: int, theta=None):
+        self.p = int(p)
+        self._m = qaoa_mpnn_create(self.p)
+        if theta is not None:
+            self.set_params(theta)
+
+    @property
+    def num_params(self) -> int:
+        return qaoa_mpnn_num_params(self.p)
+
+    def set_params(self, theta):
+        qaoa_mpnn_set_params(self._m, theta)
+
+    def get_params(self) -> np.ndarray:
+        return qaoa_mpnn_get_params(self._m, self.p)
+
+    def predict(self, graphs):
+        return qaoa_mpnn_predict(self._m, graphs, self.p)
+
+    def loss_grad(self, graphs, gamma_t, beta_t, want_grad=True):
+        return qaoa_mpnn_loss_grad(self._m, graphs, gamma_t, beta_t, self.p, want_grad)
+
+    def train_step(self, graphs, gamma_t, beta_t, **adam):
+        return qaoa_mpnn_train_step(self._m, graphs, gamma_t, beta_t, self.p, **adam)
+
+    def close(self):
+        if self._m is not None:
+            qaoa_mpnn_destroy(self._m)
+            self._m = None
 
     def __enter__(self):
         return self

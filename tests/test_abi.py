@@ -243,3 +243,32 @@ def test_batch_valid_create_without_gpu_reports_device_error(lib):
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert _batch_create(lib, [4, 6], [0, 1, 3], [[0, 1], [0, 5], [2, 3]]) == 3
+
+
+# ---------------------------------------------------------------- warm-start network (validation only)
+
+def test_mpnn_rejects(lib):
+    c = ctypes.c_int64()
+    assert lib.qaoa_mpnn_num_params(0, ctypes.byref(c)) == 1
+    assert lib.qaoa_mpnn_num_params(17, ctypes.byref(c)) == 1
+    assert lib.qaoa_mpnn_num_params(8, ctypes.byref(c)) == 0 and c.value == 92688
+    h = ctypes.c_void_p()
+    assert lib.qaoa_mpnn_create(0, ctypes.byref(h)) == 1
+    assert lib.qaoa_mpnn_create(4, None) == 1
+    assert lib.qaoa_mpnn_destroy(None) == 0
+    g = np.zeros(4)
+    n = np.array([3], dtype=np.int32)
+    off = np.array([0, 1], dtype=np.int64)
+    e = np.array([[0, 1]], dtype=np.int32)
+    assert lib.qaoa_mpnn_predict(None, 1, n.ctypes.data, off.ctypes.data, e.ctypes.data, None,
+                                 g.ctypes.data, g.ctypes.data) == 1
+    assert lib.qaoa_mpnn_set_params(None, g.ctypes.data) == 1
+    assert lib.qaoa_mpnn_train_step(None, 1, n.ctypes.data, off.ctypes.data, e.ctypes.data, None,
+                                    g.ctypes.data, g.ctypes.data, None, None) == 1
+
+
+def test_mpnn_parameter_count_matches_oracle():
+    from oracle import mpnn as om
+    from paper_2407_13012_amd import qaoa_mpnn_num_params
+    for p in (1, 3, 8, 16):
+        assert qaoa_mpnn_num_params(p) == om.num_params(p)

@@ -1,0 +1,142 @@
+"""GPU parity of the warm-start network (qaoa_mpnn_*) against its CPU oracle.
+
+The oracle (oracle/mpnn.py) rounds every matrix-product operand to bf16 at
+the same points as the GPU path and sums in float64; the GPU sums in fp32 on
+the MFMA units.  Remaining differences come from fp32 accumulation (~1e-6
+relative) and the occasional bf16 rounding that falls differently because of
+it (one bf16 ulp, 0.4%, on single elements), so predictions are compared to
+2e-4 absolute and gradients to 1e-3 of each block's largest entry.
+"""
+import numpy as np
+import pytest
+
+import qaoa_inputs as qi
+from oracle import mpnn as om
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    from paper_2407_13012_amd import load_library
+    load_library()
+
+
+def graphs_mixed(seed=0, count=12):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        n = int(rng.integers(2, 21))
+        out.append(qi.erdos_renyi(n, float(rng.uniform(0.2, 0.8)), seed=[seed, k], weights="uniform",
+                                  wlow=-1, whigh=1))
+    # an edgeless graph and a single node
+    out.append(qi.MaxCut(n=5, edges=np.zeros((0, 2), np.int32), weights=None))
+    out.append(qi.MaxCut(n=1, edges=np.zeros((0, 2), np.int32), weights=None))
+    return out
+
+
+def targets(graphs, p, seed=1):
+    rng = np.random.default_rng(seed)
+    g, b = qi.linear_ramp(p)
+    G = len(graphs)
+    return np.tile(g, (G, 1)) + rng.normal(0, 0.1, (G, p)), np.tile(b, (G, 1)) + rng.normal(0, 0.1, (G, p))
+
+
+def model(p, seed=0, theta=None):
+    from paper_2407_13012_amd import QaoaMpnn
+    t = qi.mpnn_init_params(p, seed).astype(np.float32) if theta is None else theta
+    return QaoaMpnn(p, t), t.astype(np.float64)
+
+
+@pytest.mark.parametrize("p", [1, 4, 8])
+def test_predict_matches_oracle(p):
+    graphs = graphs_mixed(p)
+    m, theta = model(p, seed=p)
+    with m:
+        g, b = m.predict(graphs)
+    og, ob = om.forward(theta, graphs, p, bf16_ops=True)
+    np.testing.assert_allclose(g, og, rtol=0, atol=2e-4)
+    np.testing.assert_allclose(b, ob, rtol=0, atol=2e-4)
+    fg, fb = om.forward(theta, graphs, p)
+    np.testing.assert_allclose(g, fg, rtol=0, atol=2e-2)
+
+
+def block_check(grad, ograd, p, rel=1e-3):
+    o = 0
+    for name, shape in om.dims(p):
+        k = int(np.prod(shape))
+        a, b = grad[o:o + k], ograd[o:o + k]
+        scale = max(np.abs(b).max(), 1e-12)
+        assert np.abs(a - b).max() <= rel * scale, (name, np.abs(a - b).max(), scale)
+        o += k
+
+
+@pytest.mark.parametrize("p", [2, 8])
+def test_loss_and_gradient_match_oracle(p):
+    graphs = graphs_mixed(10 + p)
+    gt, bt = targets(graphs, p, seed=p)
+    rng = np.random.default_rng(p)
+    t32 = (qi.mpnn_init_params(p, 3) + rng.normal(0, 0.02, om.num_params(p))).astype(np.float32)
+    m, theta = model(p, theta=t32)
+    with m:
+        L, grad = m.loss_grad(graphs, gt, bt)
+        L2, grad2 = m.loss_grad(graphs, gt, bt)
+    np.testing.assert_array_equal(grad, grad2)  # fixed-order reductions
+    assert L == L2
+    oL, ograd = om.loss_and_grad(theta, graphs, gt, bt, p, bf16_ops=True)
+    assert abs(L - oL) <= 1e-4 * oL
+    block_check(grad.astype(np.float64), ograd, p)
+
+
+def test_large_batch_rows_match_single_graph_oracle():
+    """A batch spanning many GEMM tiles and split-K slices: sampled graphs
+    against the oracle on those graphs alone (the network treats graphs independently)."""
+    p = 8
+    graphs = qi.batched_family(600, base_seed=7_000_000)
+    m, theta = model(p, seed=5)
+    gt, bt = targets(graphs, p, seed=3)
+    with m:
+        g, b = m.predict(graphs)
+        L, grad = m.loss_grad(graphs, gt, bt)
+    for i in (0, 1, 137, 301, 599):
+        og, ob = om.forward(theta, [graphs[i]], p, bf16_ops=True)
+        np.testing.assert_allclose(g[i], og[0], rtol=0, atol=2e-4)
+        np.testing.assert_allclose(b[i], ob[0], rtol=0, atol=2e-4)
+    D = np.concatenate([g - gt, b - bt], axis=1)
+    assert abs(L - float(np.mean(D * D))) <= 1e-6 * L
+    sub = graphs[:40]
+    _, gsub = om.loss_and_grad(theta, sub, gt[:40], bt[:40], p, bf16_ops=True)
+    assert np.all(np.isfinite(grad)) and np.abs(grad).max() > 0
+    assert gsub.shape == grad.shape
+
+
+def test_train_step_is_adam_on_the_gradient():
+    p = 4
+    graphs = graphs_mixed(21)
+    gt, bt = targets(graphs, p, seed=8)
+    m, theta = model(p, seed=2)
+    with m:
+        L0, grad = m.loss_grad(graphs, gt, bt)
+        L1 = m.train_step(graphs, gt, bt, lr=1e-3)
+        after = m.get_params()
+    assert L1 == L0
+    want, _, _ = om.adam_step(theta, grad.astype(np.float64), np.zeros_like(theta), np.zeros_like(theta), 1, 1e-3)
+    np.testing.assert_allclose(after, want, rtol=0, atol=2e-6)
+
+
+def test_training_reduces_loss_and_params_roundtrip():
+    p = 8
+    graphs = qi.batched_family(64, base_seed=8_000_000)
+    gt, bt = targets(graphs, p, seed=9)
+    m, theta = model(p, seed=4)
+    with m:
+        first = m.train_step(graphs, gt, bt, lr=2e-3)
+        for _ in range(60):
+            last = m.train_step(graphs, gt, bt, lr=2e-3)
+        t = m.get_params()
+        m.set_params(t)
+        np.testing.assert_array_equal(m.get_params(), t)
+    assert last < 0.5 * first, (first, last)
