@@ -139,6 +139,28 @@ def batch_leg(count: int, p: int, steps: int, log) -> dict:
     }
 
 
+WARMSTART_PARAMS = os.path.join(ROOT, "paper_2407_13012_amd", "tuning", "mpnn_p8.npy")
+
+
+def warmstart_leg(count: int, log) -> dict:
+    """Time-to-ratio of learned vs plain starts: L-BFGS (one qaoa_gradient per
+    evaluation) from the linear ramp and from the trained network's angles on
+    held-out ER(24, 0.5) graphs, p = 8; evaluations and wall time until the
+    plain run's final approximation ratio minus 0.005 is reached."""
+    import numpy as np
+
+    import qaoa_inputs as qi
+    from paper_2407_13012_amd import warmstart as ws
+
+    if not os.path.exists(WARMSTART_PARAMS):
+        return {"skipped": "no trained parameters"}
+    params = np.load(WARMSTART_PARAMS, allow_pickle=False)
+    graphs = qi.warmstart_eval_graphs(count)
+    res = ws.evaluate(params, graphs, 8, log=log)
+    res.pop("rows")
+    return res
+
+
 def cpu_baseline(inst_fn, p_n, full_n, gamma, beta):
     import oracle
     inst = inst_fn(p_n)["instance"]
@@ -170,6 +192,8 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--no-warmstart", action="store_true")
+    ap.add_argument("--warmstart-graphs", type=int, default=16)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="first run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -281,6 +305,10 @@ def main() -> int:
     if not args.no_batch:
         extra["batch"] = batch_leg(args.batch_graphs, 4, args.batch_steps,
                                    lambda m: print(m, file=sys.stderr, flush=True))
+
+    if not args.no_warmstart:
+        extra["warmstart"] = warmstart_leg(args.warmstart_graphs,
+                                           lambda m: print(m, file=sys.stderr, flush=True))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -312,8 +312,9 @@ qaoa_status qaoa_batch_destroy(qaoa_batch b);
  * batched engine) can start near good angles instead of at the linear ramp of
  * Sec. II (QAOA background: the constant-speed schedule).
  *
- *   node input   x_v = (deg_v / 8, wdeg_v / 8, 1, 0 ... 0), 32 features, with
- *                deg_v the number of incident edges and wdeg_v their weight sum
+ *   node input   x_v = (deg_v / 8, wdeg_v / 8, 1, sqdeg_v / 8, 0 ... 0), 32
+ *                features: deg_v the number of incident edges, wdeg_v the sum
+ *                of their weights, sqdeg_v the sum of their squared weights
  *   layer l      H' = ReLU([H | A H] W_l^T + b_l), l = 0, 1, 2, width 128,
  *                A the symmetric weighted adjacency
  *   readout      g = mean of H over the graph's nodes

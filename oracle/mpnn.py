@@ -6,8 +6,9 @@ weighted graph.  Only the test-suite may import this module; it shares no code
 with the HIP path.
 
 Network (all sizes fixed: hidden width 128, three message-passing layers):
-  node input   x_v = (deg_v / 8, wdeg_v / 8, 1, 0, ..., 0)  (width 32), with
-               deg_v the number of incident edges and wdeg_v their weight sum
+  node input   x_v = (deg_v / 8, wdeg_v / 8, 1, sqdeg_v / 8, 0, ..., 0)  (width 32),
+               with deg_v the number of incident edges, wdeg_v the sum of
+               their weights and sqdeg_v the sum of their squared weights
   layer l      H' = ReLU([H | A H] W_l^T + b_l),  A the symmetric weighted
                adjacency (A[i][j] = A[j][i] = sum of w over edges {i, j})
   readout      g = mean over the graph's nodes of H after layer 3
@@ -91,8 +92,11 @@ def graph_batch(graphs: Sequence):
             X[o + j, 0] += 1.0
             X[o + i, 1] += wk
             X[o + j, 1] += wk
+            X[o + i, 3] += wk * wk
+            X[o + j, 3] += wk * wk
     X[:, 0] /= 8.0
     X[:, 1] /= 8.0
+    X[:, 3] /= 8.0
     X[:, 2] = 1.0
     return off, A, X
 

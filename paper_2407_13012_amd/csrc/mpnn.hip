@@ -2,7 +2,7 @@
 // QAOA angles, trained and evaluated entirely with the kernels below.
 //
 // Network (hidden width 128, three message-passing layers, depth-p output):
-//   x_v = (deg_v / 8, wdeg_v / 8, 1, 0 ... 0)                  (32 features)
+//   x_v = (deg_v / 8, wdeg_v / 8, 1, sqdeg_v / 8, 0 ... 0)      (32 features)
 //   H'  = ReLU([H | A H] W_l^T + b_l)                            (l = 0, 1, 2)
 //   g   = mean of H over the graph's nodes
 //   Y   = ReLU(g W_h1^T + b_h1) W_h2^T + b_h2                    (2p outputs)
@@ -179,9 +179,9 @@ __global__ __launch_bounds__(256) void k_features(const int32_t *rowp, const flo
     if (v >= N) return;
     float x = 0.f;
     if (f == 0) x = (float)(rowp[v + 1] - rowp[v]) / 8.f;
-    if (f == 1) {
+    if (f == 1 || f == 3) {
         float s = 0.f;
-        for (int j = rowp[v]; j < rowp[v + 1]; ++j) s += val[j];
+        for (int j = rowp[v]; j < rowp[v + 1]; ++j) s += f == 1 ? val[j] : val[j] * val[j];
         x = s / 8.f;
     }
     if (f == 2) x = 1.f;

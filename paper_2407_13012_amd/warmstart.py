@@ -67,7 +67,7 @@ def build_dataset(graphs, p: int, steps: int, tuned: bool = True, log=print) -> 
 
 
 def train(graphs, gamma, beta, p: int, epochs: int = 30, batch: int = 256, lr: float = 2e-3,
-          seed: int = 0, val_frac: float = 0.1, theta0=None, log=print):
+          seed: int = 0, val_frac: float = 0.1, theta0=None, log=print, log_every: int = 1):
     """Fit the network to (graphs -> gamma, beta).  Returns (params, history)."""
     from qaoa_inputs import mpnn_init_params  # seeded initial weights (inputs, no network arithmetic)
     rng = np.random.default_rng(seed)
@@ -92,7 +92,8 @@ def train(graphs, gamma, beta, p: int, epochs: int = 30, batch: int = 256, lr: f
                 losses.append(m.train_step([graphs[i] for i in idx], gamma[idx], beta[idx], lr=lr_ep))
             vl, _ = m.loss_grad(vg, gamma[val], beta[val], want_grad=False)
             hist.append({"epoch": ep, "train_loss": float(np.mean(losses)), "val_loss": vl})
-            log(f"[warmstart] epoch {ep}: train {np.mean(losses):.3e} val {vl:.3e}")
+            if ep % log_every == 0 or ep == epochs:
+                log(f"[warmstart] epoch {ep}: train {np.mean(losses):.3e} val {vl:.3e}")
         secs = time.perf_counter() - t0
         params = m.get_params()
     return params, {"history": hist, "train_seconds": secs, "train_graphs": int(len(tr)), "val_graphs": int(nval)}
@@ -174,9 +175,12 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--out", default="warmstart_out")
     ap.add_argument("--train-graphs", type=int, default=4096)
-    ap.add_argument("--train-steps", type=int, default=200)
+    ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--p", type=int, default=8)
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--min-ratio", type=float, default=0.5)
     ap.add_argument("--eval-graphs", type=int, default=512)
     ap.add_argument("--eval-n", type=int, default=24)
     ap.add_argument("--max-iter", type=int, default=200)
@@ -192,16 +196,24 @@ def main(argv=None) -> int:
     save_dataset(os.path.join(args.out, f"dataset_p{args.p}.npz"), graphs, args.p, ds["gamma"], ds["beta"],
                  ds["e_first"], ds["e_last"], ds["cmax"],
                  meta={"adam_steps": args.train_steps, "engine_seconds": ds["seconds"]})
-    log(f"[warmstart] dataset mean ratio {np.mean(ds['e_last'] / ds['cmax']):.4f} "
-        f"(start {np.mean(ds['e_first'] / ds['cmax']):.4f})")
-    params, info = train(graphs, ds["gamma"], ds["beta"], args.p, epochs=args.epochs, log=log)
+    log(f"[warmstart] dataset median ratio {np.median(ds['e_last'] / ds['cmax']):.4f} "
+        f"(start {np.median(ds['e_first'] / ds['cmax']):.4f})")
+    # graphs whose optimisation stayed poor (tiny max C, or a run that did not
+    # reach min_ratio) carry little information about good angles
+    ratio = np.where(ds["cmax"] > 1e-9, ds["e_last"] / np.maximum(ds["cmax"], 1e-9), 0.0)
+    keep = np.nonzero(ratio >= args.min_ratio)[0]
+    log(f"[warmstart] training on {keep.size} of {len(graphs)} graphs (final ratio >= {args.min_ratio})")
+    params, info = train([graphs[i] for i in keep], ds["gamma"][keep], ds["beta"][keep], args.p,
+                         epochs=args.epochs, batch=args.batch, lr=args.lr, log=log,
+                         log_every=max(1, args.epochs // 20))
     np.save(os.path.join(args.out, f"mpnn_p{args.p}.npy"), params)
     ev_graphs = qi.warmstart_eval_graphs(args.eval_graphs, args.eval_n)
     res = evaluate(params, ev_graphs, args.p, max_iter=args.max_iter, log=log)
     res["training"] = info
     res["dataset"] = {"graphs": len(graphs), "adam_steps": args.train_steps, "engine_seconds": ds["seconds"],
-                      "mean_ratio_start": float(np.mean(ds["e_first"] / ds["cmax"])),
-                      "mean_ratio_final": float(np.mean(ds["e_last"] / ds["cmax"]))}
+                      "median_ratio_start": float(np.median(ds["e_first"] / ds["cmax"])),
+                      "median_ratio_final": float(np.median(ds["e_last"] / ds["cmax"])),
+                      "training_graphs_kept": int(keep.size)}
     with open(os.path.join(args.out, "warmstart_eval.json"), "w") as fh:
         json.dump(res, fh, indent=1)
     summary = {k: v for k, v in res.items() if k != "rows"}
