@@ -10,7 +10,11 @@ qaoa_gradient: E and all 2p partial derivatives.
 Prints one JSON line.  Besides the headline throughput it reports the
 roofline of the dominant kernel (HIP events bracketing every pass launch on the
 library's stream, divided into the pass's algorithmic bytes) and the CPU
-oracle's throughput on a bounded sample of the same workload.
+oracle's throughput on a bounded sample of the same workload.  Under "extra":
+the complex64 variant, 10^6-shot sampling, the batched engine on 4096 graphs of
+n ~ U{10..20} (p = 4, 100 Adam steps each, one persistent launch), and the
+time-to-ratio of learned versus linear-ramp starts on held-out ER(24, 0.5)
+graphs (p = 8, a sample of the evaluation set).
 """
 from __future__ import annotations
 

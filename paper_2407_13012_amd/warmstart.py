@@ -153,8 +153,9 @@ def evaluate(params, graphs, p: int, tol: float = 0.005, max_iter: int = 200, gt
                          evals_learned=len(tr_learn) + 2, used_learned_start=bool(E_l0 >= E_r0)))
         if log and (i % 32 == 0 or i == len(graphs) - 1):
             log(f"[warmstart] eval {i + 1}/{len(graphs)}: r_plain {r_plain:.4f} r_learned {r_learn:.4f}")
-    def tot(k):
-        return int(sum(r[k] for r in rows if r[k] is not None))
+    def tot(k, full=None):
+        # a run that never reaches the target is charged all of its evaluations
+        return int(sum(r[k] if r[k] is not None else r[full] for r in rows if r[k] is not None or full))
     reached = [r for r in rows if r["evals_learned_to_target"] is not None]
     return {
         "graphs": len(rows), "p": p, "tolerance": tol,
@@ -163,8 +164,8 @@ def evaluate(params, graphs, p: int, tol: float = 0.005, max_iter: int = 200, gt
         "mean_start_ratio_ramp": float(np.mean([r["r_start_ramp"] for r in rows])),
         "mean_start_ratio_learned": float(np.mean([r["r_start_learned"] for r in rows])),
         "total_evals_plain": tot("evals_plain"),
-        "total_evals_plain_to_target": tot("evals_plain_to_target"),
-        "total_evals_learned_to_target": tot("evals_learned_to_target"),
+        "total_evals_plain_to_target": tot("evals_plain_to_target", "evals_plain"),
+        "total_evals_learned_to_target": tot("evals_learned_to_target", "evals_learned"),
         "learned_reached_target": len(reached),
         "seconds_plain": t_plain, "seconds_learned": t_learned + t_predict, "seconds_predict": t_predict,
         "rows": rows,

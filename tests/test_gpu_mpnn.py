@@ -143,3 +143,19 @@ def test_training_reduces_loss_and_params_roundtrip():
         m.set_params(t)
         np.testing.assert_array_equal(m.get_params(), t)
     assert last < 0.7 * first, (first, last)
+
+
+def test_trained_network_saves_gradient_evaluations():
+    """The committed network (trained on the batched engine's p = 8 optima of
+    n ~ U{10..20} graphs) against linear-ramp starts on held-out ER(24, 0.5)
+    graphs under the same L-BFGS: it starts higher, ends at least as high
+    (within 0.005) and needs fewer E+G evaluations to reach the plain run's
+    final ratio minus 0.005."""
+    import os
+    from paper_2407_13012_amd import warmstart as ws
+    path = os.path.join(os.path.dirname(ws.__file__), "tuning", "mpnn_p8.npy")
+    params = np.load(path, allow_pickle=False)
+    res = ws.evaluate(params, qi.warmstart_eval_graphs(12), 8, log=None)
+    assert res["mean_start_ratio_learned"] > res["mean_start_ratio_ramp"]
+    assert res["mean_ratio_learned"] >= res["mean_ratio_plain"] - 0.005
+    assert res["total_evals_learned_to_target"] < res["total_evals_plain_to_target"]
