@@ -232,31 +232,19 @@ qaoa_status take_event(qaoa_handle h, hipEvent_t *ev)
     return QAOA_OK;
 }
 
-qaoa_status run_pass(qaoa_handle h, int mode, const qk::PassArgs &a_in)
+qaoa_status run_pass(qaoa_handle h, int mode, const qk::PassArgs &a)
 {
-    qk::PassArgs a = a_in;
-    const int kind = mode == qk::kTurnPhase ? qk::kTurn : mode;  // reported with the turn passes
-    const double bytes = h->profiling ? pass_bytes(h, mode, a) : 0.0;
-    // A plain forward pass runs on two tiles per workgroup (more bytes in flight);
-    // the XCD grouping is re-derived for the halved grid.
-    const uint64_t T = nblocks(h->n);
-    const uint32_t extra = qk::kPhaseIn | qk::kEOut | qk::kInit | qk::kNoStore;
-    if (mode == qk::kFwd && T >= 2 && !(a.flags & extra)) {
-        mode = qk::kFwd2;
-        uint32_t g = a.xcd_g;
-        while (g && (T / 2) % (8ull << g)) --g;
-        a.xcd_g = g;
-    }
     if (!h->profiling) {
-        HIPCHECK(h, qk::launch_pass(mode, c64(h), a, T, h->stream));
+        HIPCHECK(h, qk::launch_pass(mode, c64(h), a, nblocks(h->n), h->stream));
         return QAOA_OK;
     }
-    qaoa_handle_s::Pending pd{kind, bytes, nullptr, nullptr};
+    const int kind = mode == qk::kTurnPhase ? qk::kTurn : mode;  // reported with the turn passes
+    qaoa_handle_s::Pending pd{kind, pass_bytes(h, mode, a), nullptr, nullptr};
     qaoa_status st = take_event(h, &pd.t0);
     if (st == QAOA_OK) st = take_event(h, &pd.t1);
     if (st != QAOA_OK) return st;
     HIPCHECK(h, hipEventRecord(pd.t0, h->stream));
-    HIPCHECK(h, qk::launch_pass(mode, c64(h), a, T, h->stream));
+    HIPCHECK(h, qk::launch_pass(mode, c64(h), a, nblocks(h->n), h->stream));
     HIPCHECK(h, hipEventRecord(pd.t1, h->stream));
     h->pending.push_back(pd);
     return QAOA_OK;

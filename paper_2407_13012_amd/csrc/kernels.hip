@@ -59,19 +59,6 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
     }
 }
 
-// Paired plain forward pass: workgroup b takes tiles 2q and 2q + 1, q the
-// XCD-remapped index of b (so 2^(G+1) consecutive tiles share an XCD).
-template <typename R, bool TM>
-__global__ __launch_bounds__(kThreads) void k_pass2(PassArgs a)
-{
-    __shared__ typename Tr<R>::V lds[kLdsSlots];
-    const uint64_t b = blockIdx.x;
-    const uint32_t G = a.xcd_g;
-    const uint64_t q = G ? ((b & ~((8ull << G) - 1ull)) | ((b & 7ull) << G) | ((b >> 3) & ((1ull << G) - 1ull)))
-                         : b;
-    tile_pass_fwd2<R, TM>(a, 2 * q, 2 * q + 1, lds);
-}
-
 // ------------------------------------------------------------ reductions
 
 // out[k] = sum_{i < count} parts[k * stride + i], one workgroup per slot, fixed order.
@@ -425,8 +412,6 @@ template <typename R, bool TM>
 static void launch_pass_t(int mode, const PassArgs &a, dim3 grid, hipStream_t s)
 {
     if (mode == kFwd) hipLaunchKernelGGL((k_pass<R, kFwd, TM>), grid, dim3(kThreads), 0, s, a);
-    else if (mode == kFwd2)
-        hipLaunchKernelGGL((k_pass2<R, TM>), dim3(grid.x / 2), dim3(kThreads), 0, s, a);
     else if (mode == kTurn) hipLaunchKernelGGL((k_pass<R, kTurn, TM>), grid, dim3(kThreads), 0, s, a);
     else if (mode == kTurnPhase)
         hipLaunchKernelGGL((k_pass<R, kTurnPhase, TM>), grid, dim3(kThreads), 0, s, a);

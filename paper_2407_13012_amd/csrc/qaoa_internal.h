@@ -20,8 +20,7 @@ enum PassMode : int {
     kFwd = 0,   // one vector: [init|load] [phase] mixer [E] store
     kTurn = 1,  // last forward group fused with the first backward group
     kBwd = 2,   // two vectors: mixer^dag with <lam|X_j|phi>, [phase^dag with <lam|C|phi>]
-    kTurnPhase = 3, // turn pass of a one-pass layer (n <= 12): also applies and undoes the phase
-    kFwd2 = 4       // kFwd without phase, E, init or skipped store, on two tiles per workgroup
+    kTurnPhase = 3  // turn pass of a one-pass layer (n <= 12): also applies and undoes the phase
 };
 
 // Pass flags.

@@ -558,46 +558,5 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
     sums[2] = wantG ? block_sum(accG, red) : 0.0;
 }
 
-// Plain forward mixer pass (no phase, E, init or skipped store) over tiles t0
-// and t1.  The loads of both tiles are issued before either tile's arithmetic,
-// doubling the bytes each thread keeps in flight; a single-tile pass with short
-// contiguous runs leaves HBM latency exposed.
-template <typename R, bool TM>
-__device__ __forceinline__ void tile_pass_fwd2(const PassArgs &a, uint64_t t0, uint64_t t1,
-                                               typename Tr<R>::V *lds)
-{
-    using V = typename Tr<R>::V;
-    uint32_t tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
-    const uint32_t lane = tid & 63u, wave = tid >> 6;
-    const Geometry &g = a.geo;
-    const uint64_t base0 = tile_base(t0, g), base1 = tile_base(t1, g);
-    const uint32_t tmask = g.tmask;
-    const bool strm = (a.flags & kStream) != 0;
-    V *psi = (V *)a.psi;
-    const uint64_t thrA = dep(elem<0>(lane, wave, 0), g);
-    const uint64_t thrC = dep(elem<2>(lane, wave, 0), g);
-    V v0[16], v1[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v0[r] = ld(&psi[base0 | thrA | dep(elem<0>(0, 0, r), g)], strm);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v1[r] = ld(&psi[base1 | thrA | dep(elem<0>(0, 0, r), g)], strm);
-    const R mf = (R)a.mul_f, sf = (R)a.scl_f;
-    mix_stage<0, TM>(v0, mf, tmask);
-    xpose<0, 1>(v0, lds, lane, wave);
-    mix_stage<1, TM>(v0, mf, tmask);
-    xpose<1, 2>(v0, lds, lane, wave);
-    mix_stage<2, TM>(v0, mf, tmask);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) st(vscale(v0[r], sf), &psi[base0 | thrC | dep(elem<2>(0, 0, r), g)], strm);
-    mix_stage<0, TM>(v1, mf, tmask);
-    xpose<0, 1>(v1, lds, lane, wave);
-    mix_stage<1, TM>(v1, mf, tmask);
-    xpose<1, 2>(v1, lds, lane, wave);
-    mix_stage<2, TM>(v1, mf, tmask);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) st(vscale(v1[r], sf), &psi[base1 | thrC | dep(elem<2>(0, 0, r), g)], strm);
-}
-
 }  // namespace
 }  // namespace qk
