@@ -165,15 +165,18 @@ def warmstart_leg(count: int, log) -> dict:
     return res
 
 
-def cpu_baseline(inst_fn, p_n, full_n, gamma, beta):
+def cpu_baseline(inst_fn, p_n, full_n, gamma, beta, batch_sample: int = 64):
+    import numpy as np
+
     import oracle
+    import qaoa_inputs as qi
     inst = inst_fn(p_n)["instance"]
     C = oracle.cost_of(inst)
     t0 = time.perf_counter()
     oracle.gradient(p_n, C, gamma, beta)
     dt = time.perf_counter() - t0
     scale = 2.0 ** (full_n - p_n)
-    return {
+    out = {
         "value": 1.0 / (dt * scale),
         "unit": "grad_evals/s",
         "cores": oracle.num_threads(),
@@ -181,6 +184,18 @@ def cpu_baseline(inst_fn, p_n, full_n, gamma, beta):
         "sample": (f"one oracle E+G ({dt:.2f} s) of the n={p_n} member of the same QUBO family "
                    f"(p={len(gamma)}), scaled by 2^{full_n - p_n} to n={full_n} (extrapolated)"),
     }
+    if batch_sample:
+        # batched-engine workload: every 64th graph of the 4096-graph family, p = 4, one E+G each
+        graphs = qi.batched_family(4096)[::4096 // batch_sample]
+        g, b = qi.linear_ramp(4)
+        t0 = time.perf_counter()
+        for gr in graphs:
+            oracle.gradient(gr.n, oracle.cost_of(gr), g, b)
+        tb = time.perf_counter() - t0
+        out["batch"] = {"value": len(graphs) / tb, "unit": "grad_evals/s",
+                        "sample": f"one oracle E+G of each of {len(graphs)} evenly spaced graphs of the "
+                                  f"n ~ U{{10..20}} family at p=4 ({tb:.2f} s)"}
+    return out
 
 
 def main() -> int:

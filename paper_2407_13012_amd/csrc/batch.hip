@@ -506,9 +506,20 @@ qaoa_status qaoa_batch_run(qaoa_batch b, const double *gamma0, const double *bet
     for (size_t i = 0; i < np; ++i)
         if (!std::isfinite(gamma0[i]) || !std::isfinite(beta0[i]))
             return bfail(QAOA_ERR_INVALID_ARGUMENT, "angles must be finite");
-    int old = -1;
-    (void)hipGetDevice(&old);
-    if (old != b->device) (void)hipSetDevice(b->device);
+    // the batch's device is current for the call and the caller's restored after it
+    struct DeviceScope {
+        int old = -1;
+        explicit DeviceScope(int dev)
+        {
+            if (hipGetDevice(&old) != hipSuccess) old = -1;
+            if (old != dev) (void)hipSetDevice(dev);
+        }
+        ~DeviceScope()
+        {
+            int cur = -1;
+            if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+        }
+    } scope(b->device);
     qk::BatchArgs &A = b->args;
     BCHECK(b, hipMemcpyAsync(A.gamma, gamma0, np * 8, hipMemcpyHostToDevice, b->stream));
     BCHECK(b, hipMemcpyAsync(A.beta, beta0, np * 8, hipMemcpyHostToDevice, b->stream));
@@ -523,7 +534,6 @@ qaoa_status qaoa_batch_run(qaoa_batch b, const double *gamma0, const double *bet
     if (e_first) BCHECK(b, hipMemcpyAsync(e_first, A.e_first, b->count * 8, hipMemcpyDeviceToHost, b->stream));
     if (e_last) BCHECK(b, hipMemcpyAsync(e_last, A.e_last, b->count * 8, hipMemcpyDeviceToHost, b->stream));
     BCHECK(b, hipStreamSynchronize(b->stream));
-    if (old >= 0 && old != b->device) (void)hipSetDevice(old);
     return QAOA_OK;
 }
 

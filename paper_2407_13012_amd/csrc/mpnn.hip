@@ -497,8 +497,6 @@ qaoa_status ensure_ws(qaoa_mpnn m, int G, int N, int E2)
         *it.ptr = c;
         c += align256(it.bytes);
     }
-    // the padding columns of XC0 and the padded outputs stay zero
-    MCHECK(m, hipMemsetAsync(m->XC[0], 0, Nc * 2 * qm::kFin * 2, m->stream));
     m->ws_graphs = Gc;
     m->ws_nodes = Nc;
     m->ws_edges = Ec;
