@@ -382,6 +382,28 @@ qaoa_status qaoa_mpnn_train_step(qaoa_mpnn m, int32_t count, const int32_t *n, c
                                  const int32_t *edges, const double *w, const double *gamma_t,
                                  const double *beta_t, const qaoa_mpnn_adam *opt, double *loss);
 
+/*
+ * Device-memory provider for handles (e.g. a framework's caching allocator, so
+ * that the simulator's buffers share its pool).  alloc returns `bytes` of
+ * device memory on the current device, usable on `stream` (the handle's
+ * stream), or NULL on failure (reported as QAOA_ERR_OUT_OF_MEMORY); free
+ * releases it (called after the handle's stream has been synchronised).
+ */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *ptr, size_t bytes, void *stream, void *user);
+    void *user;
+} qaoa_allocator;
+
+/*
+ * Allocator for the state, cost diagonal, adjoint vector and scratch buffers
+ * of handles created afterwards on the calling thread; each handle keeps the
+ * allocator it was created with until qaoa_destroy.  NULL restores
+ * hipMalloc/hipFree.  With an allocator set, the free-memory pre-checks are
+ * left to it.  Errors: INVALID_ARGUMENT if alloc or free is NULL.
+ */
+qaoa_status qaoa_set_allocator(const qaoa_allocator *a);
+
 /* Static English description of a status code. */
 const char *qaoa_status_string(qaoa_status s);
 

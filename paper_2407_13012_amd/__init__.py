@@ -16,6 +16,10 @@ from ._binding import (  # noqa: F401
     QaoaHandle,
     QaoaBatch,
     QaoaMpnn,
+    Allocator,
+    qaoa_set_allocator,
+    torch_allocator,
+    use_torch_allocator,
     MpnnAdam,
     qaoa_mpnn_create,
     qaoa_mpnn_destroy,
@@ -54,4 +58,4 @@ from ._binding import (  # noqa: F401
 )
 
 __all__ = [name for name in dir() if name.startswith("qaoa_")] + [
-    "QaoaHandle", "QaoaBatch", "QaoaMpnn", "MpnnAdam", "BatchOptions", "batch_options", "QaoaError", "QAOA_C128", "QAOA_C64", "load_library", "library_path"]
+    "QaoaHandle", "QaoaBatch", "QaoaMpnn", "Allocator", "torch_allocator", "use_torch_allocator", "MpnnAdam", "BatchOptions", "batch_options", "QaoaError", "QAOA_C128", "QAOA_C64", "load_library", "library_path"]

@@ -34,6 +34,15 @@ class BatchOptions(ctypes.Structure):
                 ("waves_per_simd", ctypes.c_int32), ("group_by_n", ctypes.c_int32 * (BATCH_MAX_QUBITS + 1))]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    """Mirror of qaoa_allocator."""
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
 class MpnnAdam(ctypes.Structure):
     """Mirror of qaoa_mpnn_adam."""
     _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
@@ -91,6 +100,7 @@ def load_library() -> ctypes.CDLL:
         "qaoa_batch_create": [i32, vp, vp, vp, vp, i32, ctypes.POINTER(BatchOptions), pvp],
         "qaoa_batch_run": [vp, vp, vp, vp, vp, vp, vp],
         "qaoa_batch_destroy": [vp],
+        "qaoa_set_allocator": [ctypes.POINTER(Allocator)],
         "qaoa_mpnn_num_params": [i32, ctypes.POINTER(i64)],
         "qaoa_mpnn_create": [i32, pvp],
         "qaoa_mpnn_destroy": [vp],
@@ -489,6 +499,49 @@ def qaoa_profile_read(h, kind: int):
     _check(load_library().qaoa_profile_read(h, int(kind), ctypes.byref(n), ctypes.byref(ms),
                                             ctypes.byref(by)), "qaoa_profile_read")
     return n.value, ms.value, by.value
+
+
+def qaoa_set_allocator(allocator: Optional[Allocator]) -> None:
+    """Allocator for handles created afterwards on this thread (None: hipMalloc)."""
+    lib = load_library()
+    _check(lib.qaoa_set_allocator(ctypes.byref(allocator) if allocator is not None else None),
+           "qaoa_set_allocator")
+
+
+_torch_allocator: Optional[Allocator] = None
+
+
+def torch_allocator() -> Allocator:
+    """An allocator backed by torch's caching allocator (the callbacks live for
+    the whole process, as handles may outlive any scope)."""
+    global _torch_allocator
+    if _torch_allocator is None:
+        import torch
+
+        def _alloc(nbytes, stream, _user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                          int(stream or 0))
+            except Exception:
+                return None
+
+        def _free(ptr, _nbytes, _stream, _user):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        _torch_allocator = Allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+    return _torch_allocator
+
+
+class use_torch_allocator:
+    """Context manager: handles created inside take their device buffers from
+    torch's caching allocator."""
+
+    def __enter__(self):
+        qaoa_set_allocator(torch_allocator())
+        return self
+
+    def __exit__(self, *exc):
+        qaoa_set_allocator(None)
 
 
 def qaoa_status_string(status: int) -> str:

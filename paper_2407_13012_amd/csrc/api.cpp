@@ -43,6 +43,7 @@ struct qaoa_handle_s {
     int prec = QAOA_C128;
     int device = 0;
     uint64_t N = 0;
+    qaoa_allocator alloc{};  // device-memory provider (alloc == NULL: hipMalloc / hipFree)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     void *psi = nullptr;   // state, 2^n amplitudes
@@ -69,6 +70,32 @@ struct qaoa_handle_s {
     double prof_ms[3] = {0, 0, 0};
     double prof_bytes[3] = {0, 0, 0};
 };
+
+namespace {
+
+thread_local qaoa_allocator g_alloc{};  // allocator for handles created on this thread
+
+// Device allocation through the handle's allocator.
+hipError_t dev_alloc(qaoa_handle h, void **p, size_t bytes)
+{
+    if (!h->alloc.alloc) return hipMalloc(p, bytes);
+    *p = h->alloc.alloc(bytes, (void *)h->stream, h->alloc.user);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+void dev_free(qaoa_handle h, void *p, size_t bytes)
+{
+    if (!p) return;
+    if (!h->alloc.alloc) (void)hipFree(p);
+    else h->alloc.free(p, bytes, (void *)h->stream, h->alloc.user);
+}
+
+// Free device memory for a buffer of `bytes`, or true when an allocator
+// provides the memory (it reports failure itself).
+bool fits(qaoa_handle h, double bytes, size_t fr) { return h->alloc.alloc || bytes <= (double)fr; }
+
+}  // namespace
+
 
 namespace {
 
@@ -152,13 +179,18 @@ qaoa_status check_terms(int32_t n, int64_t m, const int32_t *idx, const double *
 qaoa_status ensure_doubles(qaoa_handle h, double **buf, size_t *cap, size_t count)
 {
     if (*cap >= count) return QAOA_OK;
-    if (*buf) HIPCHECK(h, hipFree(*buf));
+    if (*buf) {
+        HIPCHECK(h, hipStreamSynchronize(h->stream));
+        dev_free(h, *buf, *cap * sizeof(double));
+    }
     *buf = nullptr;
     *cap = 0;
     size_t fr = 0, tot = 0;
     HIPCHECK(h, hipMemGetInfo(&fr, &tot));
-    if (count * sizeof(double) > fr) return fail(QAOA_ERR_OUT_OF_MEMORY, "scratch buffer does not fit");
-    HIPCHECK(h, hipMalloc((void **)buf, count * sizeof(double)));
+    if (!fits(h, (double)count * sizeof(double), fr))
+        return fail(QAOA_ERR_OUT_OF_MEMORY, "scratch buffer does not fit");
+    if (dev_alloc(h, (void **)buf, count * sizeof(double)) != hipSuccess)
+        return fail(QAOA_ERR_OUT_OF_MEMORY, "scratch buffer allocation failed");
     *cap = count;
     return QAOA_OK;
 }
@@ -315,6 +347,7 @@ qaoa_status create_common(int32_t n, int32_t precision, void *stream, qaoa_handl
     h->n = n;
     h->prec = precision;
     h->N = 1ull << n;
+    h->alloc = g_alloc;
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) {
         delete h;
@@ -328,7 +361,7 @@ qaoa_status create_common(int32_t n, int32_t precision, void *stream, qaoa_handl
     }
     const double need = (double)h->N * (double)(amp_bytes(precision) + cost_bytes(precision)) +
                         (double)nblocks(n) * 8.0 * 2 + (1 << 20);
-    if (need > (double)fr) {
+    if (!fits(h, need, fr)) {
         delete h;
         return fail(QAOA_ERR_OUT_OF_MEMORY, "state and cost diagonal do not fit in free device memory");
     }
@@ -343,10 +376,11 @@ qaoa_status create_common(int32_t n, int32_t precision, void *stream, qaoa_handl
         h->own_stream = true;
     }
     *hh = h;
-    if ((e = hipMalloc(&h->psi, h->N * amp_bytes(precision))) != hipSuccess ||
-        (e = hipMalloc(&h->cost, h->N * cost_bytes(precision))) != hipSuccess) {
+    if ((e = dev_alloc(h, &h->psi, h->N * amp_bytes(precision))) != hipSuccess ||
+        (e = dev_alloc(h, &h->cost, h->N * cost_bytes(precision))) != hipSuccess) {
         qaoa_destroy(h);
         *hh = nullptr;
+        if (e == hipErrorOutOfMemory) return fail(QAOA_ERR_OUT_OF_MEMORY, "state or cost allocation failed");
         return device_fail(nullptr, "hipMalloc", e);
     }
     qaoa_status st = ensure_doubles(h, &h->parts, &h->parts_cap, 2 * nblocks(n) + 2);
@@ -482,11 +516,11 @@ qaoa_status qaoa_destroy(qaoa_handle h)
     if (!h) return QAOA_OK;
     DeviceGuard dg(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    if (h->psi) (void)hipFree(h->psi);
-    if (h->lam) (void)hipFree(h->lam);
-    if (h->cost) (void)hipFree(h->cost);
-    if (h->parts) (void)hipFree(h->parts);
-    if (h->res) (void)hipFree(h->res);
+    dev_free(h, h->psi, h->N * amp_bytes(h->prec));
+    dev_free(h, h->lam, h->N * amp_bytes(h->prec));
+    dev_free(h, h->cost, h->N * cost_bytes(h->prec));
+    dev_free(h, h->parts, h->parts_cap * sizeof(double));
+    dev_free(h, h->res, h->res_cap * sizeof(double));
     for (auto &pd : h->pending) {
         (void)hipEventDestroy(pd.t0);
         (void)hipEventDestroy(pd.t1);
@@ -631,9 +665,10 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
     if (!h->lam) {
         size_t fr = 0, tot = 0;
         HIPCHECK(h, hipMemGetInfo(&fr, &tot));
-        if (h->N * amp_bytes(h->prec) > fr)
+        if (!fits(h, (double)h->N * amp_bytes(h->prec), fr))
             return fail(QAOA_ERR_OUT_OF_MEMORY, "adjoint vector does not fit in free device memory");
-        HIPCHECK(h, hipMalloc(&h->lam, h->N * amp_bytes(h->prec)));
+        if (dev_alloc(h, &h->lam, h->N * amp_bytes(h->prec)) != hipSuccess)
+            return fail(QAOA_ERR_OUT_OF_MEMORY, "adjoint vector allocation failed");
     }
     const uint64_t T = nblocks(h->n);
     const int nslots = 2 * p + 1;
@@ -794,5 +829,16 @@ const char *qaoa_status_string(qaoa_status s)
 }
 
 const char *qaoa_last_error_message(void) { return g_err.c_str(); }
+
+qaoa_status qaoa_set_allocator(const qaoa_allocator *a)
+{
+    if (!a) {
+        g_alloc = qaoa_allocator{};
+        return QAOA_OK;
+    }
+    if (!a->alloc || !a->free) return fail(QAOA_ERR_INVALID_ARGUMENT, "allocator needs both alloc and free");
+    g_alloc = *a;
+    return QAOA_OK;
+}
 
 }  // extern "C"

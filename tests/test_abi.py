@@ -272,3 +272,12 @@ def test_mpnn_parameter_count_matches_oracle():
     from paper_2407_13012_amd import qaoa_mpnn_num_params
     for p in (1, 3, 8, 16):
         assert qaoa_mpnn_num_params(p) == om.num_params(p)
+
+
+def test_set_allocator_validation(lib):
+    from paper_2407_13012_amd import Allocator
+    from paper_2407_13012_amd._binding import ALLOC_FN
+    assert lib.qaoa_set_allocator(None) == 0
+    half = Allocator(ALLOC_FN(lambda n, s, u: None), ctypes.cast(None, type(Allocator().free)), None)
+    assert lib.qaoa_set_allocator(ctypes.byref(half)) == 1
+    assert lib.qaoa_set_allocator(None) == 0
