@@ -43,7 +43,7 @@ namespace {
 template <typename R, int MODE, bool TM>
 __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
 {
-    __shared__ typename Tr<R>::V lds[kLdsSlots];
+    __shared__ typename Tr<R>::V lds[kLdsTotal];
     const uint64_t b = blockIdx.x;
     // 2^G consecutive tiles per XCD: workgroups are dealt to the 8 XCDs in turn
     const uint32_t G = a.xcd_g;

@@ -62,6 +62,9 @@ __device__ __forceinline__ void stnt(float2 v, float2 *p)
 // groups, and the slot is additive over the thread part and the register part
 // of e, so every access is one base register plus an immediate offset.
 constexpr int kLdsSlots = kTile + kTile / 16;
+// The workgroup's LDS: the padded transpose slots plus room for the per-wave
+// partial sums of the block reduction (3 values x 4 waves of doubles).
+constexpr int kLdsTotal = kLdsSlots + 12;
 __host__ __device__ __forceinline__ constexpr uint32_t lds_slot(uint32_t e) { return e + (e >> 4); }
 
 template <int ARR>
@@ -317,6 +320,31 @@ __device__ __forceinline__ double block_sum(double x, double *scratch)
     return r;
 }
 
+// Fixed-order sums over the 256-thread block of up to three values (each as
+// block_sum would give it), valid in thread 0, with one barrier.  `red` holds
+// 12 doubles outside the transpose slots, so the caller's next LDS writes need
+// no further barrier: thread 0 reads `red` before it reaches the next one.
+__device__ __forceinline__ void block_sums3(double e, double b, double g, bool we, bool wb, bool wg,
+                                            double *red, double (&out)[3])
+{
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    if (we) e = wave_sum(e);
+    if (wb) b = wave_sum(b);
+    if (wg) g = wave_sum(g);
+    if (lane == 0) {
+        red[wave] = e;
+        red[4 + wave] = b;
+        red[8 + wave] = g;
+    }
+    __syncthreads();
+    out[0] = out[1] = out[2] = 0.0;
+    if (threadIdx.x == 0) {
+        if (we) out[0] = ((red[0] + red[1]) + red[2]) + red[3];
+        if (wb) out[1] = ((red[4] + red[5]) + red[6]) + red[7];
+        if (wg) out[2] = ((red[8] + red[9]) + red[10]) + red[11];
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T ld(const T *p, bool stream)
 {
@@ -365,6 +393,15 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
 #define ZC(r) (thrC | dep(elem<2>(0, 0, (r)), g))
 #define VA(r) (full || elem<0>(lane, wave, (r)) < lim)
 #define VC(r) (full || elem<2>(lane, wave, (r)) < lim)
+    // Block sums of the tile's E, <lam|X|phi> and <lam|C|phi> terms, taken
+    // before the final stores so that the workgroup retires right after issuing them.
+#define REDUCE()                                                                        \
+    do {                                                                                \
+        if (wantE || wantB || wantG)                                                    \
+            block_sums3(accE, accB, accG, wantE, wantB, wantG, (double *)(lds + kLdsSlots), sums); \
+        else                                                                            \
+            sums[0] = sums[1] = sums[2] = 0.0;                                          \
+    } while (0)
 
     double accE = 0.0, accB = 0.0, accG = 0.0;
     const V zero = {(R)0, (R)0};
@@ -375,6 +412,9 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
     // which optional steps this launch performs (compile-time where the mode decides)
     const bool phaseIn = MODE == kTurnPhase || (MODE == kFwd && (a.flags & kPhaseIn));
     const bool phaseOut = MODE == kTurnPhase || (MODE == kBwd && (a.flags & kPhaseOut));
+    const bool wantE = TURN || (MODE == kFwd && (a.flags & kEOut));
+    const bool wantB = MODE != kFwd;
+    const bool wantG = phaseOut;
     const bool costC = TURN || phaseOut || (MODE == kFwd && (a.flags & kEOut));
     CT cin[16], cv[16];
     if (phaseIn) {
@@ -420,6 +460,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
 #pragma unroll
                 for (int r = 0; r < 16; ++r) accE += (double)cv[r] * norm2(v[r]);
             }
+            REDUCE();
             if (!(a.flags & kNoStore)) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
@@ -465,6 +506,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                 xpose<1, 0>(l, lds, lane, wave);
                 beta_terms<0>(v, l, tmask, upow(fb, kC + 2 * kB) * upow(ff, kA + kB), accB);
                 mix_stage<0, TM>(l, mb, tmask);
+                REDUCE();
                 if (!(a.flags & kNoStore)) {
 #pragma unroll
                     for (int r = 0; r < 16; ++r)
@@ -492,6 +534,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                         l[r] = cmul(l[r], c, s);
                     }
                 }
+                REDUCE();
                 if (!(a.flags & kNoStore)) {
 #pragma unroll
                     for (int r = 0; r < 16; ++r)
@@ -534,6 +577,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                     l[r] = cmul(l[r], c, s);
                 }
         }
+        REDUCE();
         if (!(a.flags & kNoStore)) {
 #pragma unroll
             for (int r = 0; r < 16; ++r)
@@ -547,15 +591,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
 #undef ZC
 #undef VA
 #undef VC
-
-    // Fixed-order block reductions.
-    double *red = (double *)lds;  // every LDS read above completed before the last barrier
-    const bool wantE = TURN || (MODE == kFwd && (a.flags & kEOut));
-    const bool wantB = MODE != kFwd;
-    const bool wantG = phaseOut;
-    sums[0] = wantE ? block_sum(accE, red) : 0.0;
-    sums[1] = wantB ? block_sum(accB, red) : 0.0;
-    sums[2] = wantG ? block_sum(accG, red) : 0.0;
+#undef REDUCE
 }
 
 }  // namespace
