@@ -239,6 +239,36 @@ qk::PassArgs pass_args(qaoa_handle h, const qk::PassPlan &pp, double beta)
     return a;
 }
 
+// Second rotation of a layer-boundary pass (kFwdFuse / kBwdFuse): the same
+// factored form for the other layer's angle on the same target qubits.
+void set_second(qk::PassArgs &a, double beta2)
+{
+    const double c = std::cos(beta2), s = std::sin(beta2);
+    const int k = __builtin_popcount(a.geo.tmask);
+    a.tan_mode2 = std::fabs(c) >= std::fabs(s) ? 1u : 0u;
+    double ff, fb;
+    if (a.tan_mode2) {
+        a.mul_f2 = s / c;
+        a.mul_b2 = -s / c;
+        ff = fb = c;
+    } else {
+        a.mul_f2 = c / s;
+        a.mul_b2 = -c / s;
+        ff = s;
+        fb = -s;
+    }
+    a.fac_b2 = fb;
+    a.scl_f2 = a.scl_b2 = 1.0;
+    for (int i = 0; i < k; ++i) {
+        a.scl_f2 *= ff;
+        a.scl_b2 *= fb;
+    }
+}
+
+// Mixer group visited at position idx of layer l: even layers ascending, odd
+// layers descending, so that consecutive layers meet on one shared group.
+int group_at(int l, int idx, int P) { return (l % 2 == 0) ? idx : P - 1 - idx; }
+
 // Bytes a pass must move at minimum: each amplitude vector it reads and/or
 // writes once, plus one read of the cost diagonal when it applies or measures C.
 double pass_bytes(qaoa_handle h, int mode, const qk::PassArgs &a)
@@ -250,6 +280,8 @@ double pass_bytes(qaoa_handle h, int mode, const qk::PassArgs &a)
         return N * ((initd ? 0 : s) + (store ? s : 0) +
                     ((a.flags & (qk::kPhaseIn | qk::kEOut)) ? c : 0));
     if (mode == qk::kTurn || mode == qk::kTurnPhase) return N * ((initd ? 0 : s) + c + (store ? s : 0));
+    if (mode == qk::kFwdFuse) return N * (2 * s + c);
+    if (mode == qk::kBwdFuse) return N * (4 * s + c);
     return N * (2 * s + (store ? 2 * s : 0) + ((a.flags & qk::kPhaseOut) ? c : 0));
 }
 
@@ -270,7 +302,9 @@ qaoa_status run_pass(qaoa_handle h, int mode, const qk::PassArgs &a)
         HIPCHECK(h, qk::launch_pass(mode, c64(h), a, nblocks(h->n), h->stream));
         return QAOA_OK;
     }
-    const int kind = mode == qk::kTurnPhase ? qk::kTurn : mode;  // reported with the turn passes
+    // reported kinds: forward (also layer-boundary forward), turn, backward
+    const int kind = (mode == qk::kFwd || mode == qk::kFwdFuse) ? 0
+                     : (mode == qk::kTurn || mode == qk::kTurnPhase) ? 1 : 2;
     qaoa_handle_s::Pending pd{kind, pass_bytes(h, mode, a), nullptr, nullptr};
     qaoa_status st = take_event(h, &pd.t0);
     if (st == QAOA_OK) st = take_event(h, &pd.t1);
@@ -308,15 +342,27 @@ qaoa_status run_forward(qaoa_handle h, int p, const double *gamma, const double 
     const std::vector<qk::PassPlan> G = qk::plan_passes(h->n, c64(h));
     const int P = (int)G.size();
     for (int l = 0; l < p; ++l) {
-        const int gend = (l == p - 1 && skip_last) ? P - 1 : P;
-        for (int gi = 0; gi < gend; ++gi) {
+        for (int idx = 0; idx < P; ++idx) {
+            // with P >= 2, a layer's first group was applied by the previous
+            // layer's last (layer-boundary) pass
+            if (P > 1 && l > 0 && idx == 0) continue;
+            const bool last = idx == P - 1;
+            if (last && l == p - 1 && skip_last) break;  // the gradient's turn pass
+            const int gi = P > 1 ? group_at(l, idx, P) : 0;
             qk::PassArgs a = pass_args(h, G[gi], beta[l]);
-            if (gi == 0) {
+            if (P > 1 && last && l < p - 1) {
+                set_second(a, beta[l + 1]);
+                a.gamma_in = gamma[l + 1];
+                qaoa_status st = run_pass(h, qk::kFwdFuse, a);
+                if (st != QAOA_OK) return st;
+                continue;
+            }
+            if (idx == 0) {
                 a.flags |= qk::kPhaseIn;
                 a.gamma_in = gamma[l];
                 if (l == 0) a.flags |= qk::kInit;
             }
-            if (e_out && l == p - 1 && gi == gend - 1) {
+            if (e_out && l == p - 1 && last) {
                 a.flags |= qk::kEOut;
                 a.part_e = h->parts;
             }
@@ -688,7 +734,7 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
     // Turn pass: last group of layer p-1 forward, E, lam = C phi, group undone on lam.
     {
         const int l = p - 1;
-        qk::PassArgs a = pass_args(h, G[P - 1], beta[l]);
+        qk::PassArgs a = pass_args(h, G[P > 1 ? group_at(l, P - 1, P) : 0], beta[l]);
         a.part_e = slotE;
         a.part_b = slotB(l);
         if (P == 1) {
@@ -699,22 +745,38 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
         }
         if ((st = run_pass(h, P == 1 ? qk::kTurnPhase : qk::kTurn, a)) != QAOA_OK) return st;
     }
-    // Backward sweep: layer l undoes groups (last..0); group 0 also undoes the phase.
+    // Backward sweep: each layer undoes its groups in the reverse of the forward
+    // order; a layer's first group also undoes its phase and, for P >= 2 and
+    // l > 0, shares its sweep with the last group of layer l - 1.  The first
+    // pass to touch a layer's <lam|X|phi> partials overwrites them, later
+    // passes add to them (the turn pass wrote layer p-1's).
+    std::vector<char> written((size_t)p, 0);
+    written[p - 1] = 1;
     for (int l = p - 1; l >= 0; --l) {
-        const int gstart = (l == p - 1) ? P - 2 : P - 1;
-        for (int gi = gstart; gi >= 0; --gi) {
+        for (int j = 0; j < P; ++j) {
+            const int idx = P - 1 - j;
+            if (j == 0 && (l == p - 1 || P > 1)) continue;  // turn pass, or fused into layer l+1
+            const int gi = P > 1 ? group_at(l, idx, P) : 0;
             qk::PassArgs a = pass_args(h, G[gi], beta[l]);
             a.part_b = slotB(l);
-            // The first pass of a layer's sweep writes the beta partial (the turn
-            // pass does so for layer p-1); later passes add to it.
-            if (l == p - 1 || gi != P - 1) a.flags |= qk::kBetaAcc;
-            if (gi == 0) {
-                a.flags |= qk::kPhaseOut;
+            if (written[l]) a.flags |= qk::kBetaAcc;
+            written[l] = 1;
+            int mode = qk::kBwd;
+            if (idx == 0) {
                 a.gamma_out = gamma[l];
                 a.part_g = slotG(l);
-                if (l == 0) a.flags |= qk::kNoStore;
+                if (P > 1 && l > 0) {
+                    mode = qk::kBwdFuse;
+                    set_second(a, beta[l - 1]);
+                    a.part_b2 = slotB(l - 1);
+                    if (written[l - 1]) a.flags |= qk::kBetaAcc2;
+                    written[l - 1] = 1;
+                } else {
+                    a.flags |= qk::kPhaseOut;
+                    if (l == 0) a.flags |= qk::kNoStore;
+                }
             }
-            if ((st = run_pass(h, qk::kBwd, a)) != QAOA_OK) return st;
+            if ((st = run_pass(h, mode, a)) != QAOA_OK) return st;
         }
     }
     std::vector<double> r((size_t)nslots);

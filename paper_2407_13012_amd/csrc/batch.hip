@@ -127,7 +127,7 @@ __device__ __forceinline__ void run_tiles(const PassArgs &a, uint64_t T, double2
         }
         opaque(b.geo.tmask);
         opaque(b.geo.tbits);
-        double s[3];
+        double s[4];
         if (b.tan_mode) tile_pass<double, MODE, true>(b, t, lds, s);
         else tile_pass<double, MODE, false>(b, t, lds, s);
         acc[0] += s[0];

@@ -49,13 +49,36 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
     const uint32_t G = a.xcd_g;
     const uint64_t t = G ? ((b & ~((8ull << G) - 1ull)) | ((b & 7ull) << G) | ((b >> 3) & ((1ull << G) - 1ull)))
                          : b;
-    double sums[3];
+    double sums[4];
     tile_pass<R, MODE, TM>(a, t, lds, sums);
     // one partial per workgroup
     if (threadIdx.x == 0) {
         if (MODE == kTurn || MODE == kTurnPhase || (MODE == kFwd && (a.flags & kEOut))) a.part_e[b] = sums[0];
         if (MODE != kFwd) a.part_b[b] = (a.flags & kBetaAcc) ? a.part_b[b] + sums[1] : sums[1];
         if (MODE == kTurnPhase || (MODE == kBwd && (a.flags & kPhaseOut))) a.part_g[b] = sums[2];
+    }
+}
+
+// Layer-boundary passes (kFwdFuse, kBwdFuse); TM / TM2 are the factored forms
+// of the two rotations.  Same tile order and partial layout as k_pass.
+template <typename R, int MODE, bool TM, bool TM2>
+__global__ __launch_bounds__(kThreads) void k_pass_fuse(PassArgs a)
+{
+    __shared__ typename Tr<R>::V lds[kLdsTotal];
+    const uint64_t b = blockIdx.x;
+    const uint32_t G = a.xcd_g;
+    const uint64_t t = G ? ((b & ~((8ull << G) - 1ull)) | ((b & 7ull) << G) | ((b >> 3) & ((1ull << G) - 1ull)))
+                         : b;
+    if constexpr (MODE == kFwdFuse) {
+        tile_pass_fwd_fuse<R, TM, TM2>(a, t, lds);
+    } else {
+        double sums[4];
+        tile_pass<R, kBwdFuse, TM, TM2>(a, t, lds, sums);
+        if (threadIdx.x == 0) {
+            a.part_b[b] = (a.flags & kBetaAcc) ? a.part_b[b] + sums[1] : sums[1];
+            a.part_g[b] = sums[2];
+            a.part_b2[b] = (a.flags & kBetaAcc2) ? a.part_b2[b] + sums[3] : sums[3];
+        }
     }
 }
 
@@ -418,9 +441,29 @@ static void launch_pass_t(int mode, const PassArgs &a, dim3 grid, hipStream_t s)
     else hipLaunchKernelGGL((k_pass<R, kBwd, TM>), grid, dim3(kThreads), 0, s, a);
 }
 
+template <typename R, int MODE>
+static void launch_fuse_t(const PassArgs &a, dim3 grid, hipStream_t s)
+{
+    const int sel = (a.tan_mode ? 2 : 0) + (a.tan_mode2 ? 1 : 0);
+    if (sel == 3) hipLaunchKernelGGL((k_pass_fuse<R, MODE, true, true>), grid, dim3(kThreads), 0, s, a);
+    else if (sel == 2) hipLaunchKernelGGL((k_pass_fuse<R, MODE, true, false>), grid, dim3(kThreads), 0, s, a);
+    else if (sel == 1) hipLaunchKernelGGL((k_pass_fuse<R, MODE, false, true>), grid, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((k_pass_fuse<R, MODE, false, false>), grid, dim3(kThreads), 0, s, a);
+}
+
 hipError_t launch_pass(int mode, bool c64, const PassArgs &a, uint64_t nblocks, hipStream_t s)
 {
     const dim3 grid((unsigned)nblocks);
+    if (mode == kFwdFuse || mode == kBwdFuse) {
+        if (!c64) {
+            if (mode == kFwdFuse) launch_fuse_t<double, kFwdFuse>(a, grid, s);
+            else launch_fuse_t<double, kBwdFuse>(a, grid, s);
+        } else {
+            if (mode == kFwdFuse) launch_fuse_t<float, kFwdFuse>(a, grid, s);
+            else launch_fuse_t<float, kBwdFuse>(a, grid, s);
+        }
+        return hipGetLastError();
+    }
     if (!c64) {
         if (a.tan_mode) launch_pass_t<double, true>(mode, a, grid, s);
         else launch_pass_t<double, false>(mode, a, grid, s);

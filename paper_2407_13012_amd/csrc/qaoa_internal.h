@@ -20,7 +20,12 @@ enum PassMode : int {
     kFwd = 0,   // one vector: [init|load] [phase] mixer [E] store
     kTurn = 1,  // last forward group fused with the first backward group
     kBwd = 2,   // two vectors: mixer^dag with <lam|X_j|phi>, [phase^dag with <lam|C|phi>]
-    kTurnPhase = 3  // turn pass of a one-pass layer (n <= 12): also applies and undoes the phase
+    kTurnPhase = 3, // turn pass of a one-pass layer (n <= 12): also applies and undoes the phase
+    // Layer-boundary passes.  Consecutive layers visit their mixer groups in
+    // opposite orders, so the last group of layer l and the first group of
+    // layer l+1 share a geometry and one sweep serves both:
+    kFwdFuse = 4,   // group of layer l, phase of layer l+1, same group of layer l+1
+    kBwdFuse = 5    // their inverses with the <lam|X|phi> terms of both layers and <lam|C|phi>
 };
 
 // Pass flags.
@@ -31,7 +36,8 @@ enum PassFlags : int {
     kPhaseOut = 8,   // (kBwd, kTurn) accumulate Im <lam|C|phi>, then multiply both by exp(+i gamma_out C)
     kNoStore = 16,   // skip the final store (last backward pass)
     kBetaAcc = 32,   // add the <lam|X|phi> partial to the existing one instead of overwriting
-    kStream = 64     // nontemporal loads/stores (tiles with long contiguous runs)
+    kStream = 64,    // nontemporal loads/stores (tiles with long contiguous runs)
+    kBetaAcc2 = 128  // kBetaAcc for the second rotation's partials (kBwdFuse)
 };
 
 // One pass of a mixer layer.  A tile is the set of 2^12 basis indices that
@@ -85,6 +91,10 @@ struct PassArgs {
     double gamma_out;   // kPhaseOut multiplies by exp(+i gamma_out C)
     double amp0;        // 2^{-n/2}
     int flags;
+    // Second rotation of a layer-boundary pass (the other layer's angle), same form.
+    uint32_t tan_mode2;
+    double mul_f2, mul_b2, fac_b2, scl_f2, scl_b2;
+    double *part_b2;    // <lam|X|phi> partials of the second rotation's layer
 };
 
 // Launchers; all return the launch status.  `c64` selects complex64/fp32 cost.

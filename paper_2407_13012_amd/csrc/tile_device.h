@@ -63,8 +63,8 @@ __device__ __forceinline__ void stnt(float2 v, float2 *p)
 // of e, so every access is one base register plus an immediate offset.
 constexpr int kLdsSlots = kTile + kTile / 16;
 // The workgroup's LDS: the padded transpose slots plus room for the per-wave
-// partial sums of the block reduction (3 values x 4 waves of doubles).
-constexpr int kLdsTotal = kLdsSlots + 12;
+// partial sums of the block reduction (4 values x 4 waves of doubles).
+constexpr int kLdsTotal = kLdsSlots + 16;
 __host__ __device__ __forceinline__ constexpr uint32_t lds_slot(uint32_t e) { return e + (e >> 4); }
 
 template <int ARR>
@@ -320,28 +320,27 @@ __device__ __forceinline__ double block_sum(double x, double *scratch)
     return r;
 }
 
-// Fixed-order sums over the 256-thread block of up to three values (each as
+// Fixed-order sums over the 256-thread block of up to four values (each as
 // block_sum would give it), valid in thread 0, with one barrier.  `red` holds
-// 12 doubles outside the transpose slots, so the caller's next LDS writes need
+// 16 doubles outside the transpose slots, so the caller's next LDS writes need
 // no further barrier: thread 0 reads `red` before it reaches the next one.
-__device__ __forceinline__ void block_sums3(double e, double b, double g, bool we, bool wb, bool wg,
-                                            double *red, double (&out)[3])
+__device__ __forceinline__ void block_sums4(const double (&x)[4], const bool (&want)[4], double *red,
+                                            double (&out)[4])
 {
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    if (we) e = wave_sum(e);
-    if (wb) b = wave_sum(b);
-    if (wg) g = wave_sum(g);
+    double w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = want[k] ? wave_sum(x[k]) : 0.0;
     if (lane == 0) {
-        red[wave] = e;
-        red[4 + wave] = b;
-        red[8 + wave] = g;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[4 * k + wave] = w[k];
     }
     __syncthreads();
-    out[0] = out[1] = out[2] = 0.0;
-    if (threadIdx.x == 0) {
-        if (we) out[0] = ((red[0] + red[1]) + red[2]) + red[3];
-        if (wb) out[1] = ((red[4] + red[5]) + red[6]) + red[7];
-        if (wg) out[2] = ((red[8] + red[9]) + red[10]) + red[11];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        out[k] = 0.0;
+        if (threadIdx.x == 0 && want[k])
+            out[k] = ((red[4 * k] + red[4 * k + 1]) + red[4 * k + 2]) + red[4 * k + 3];
     }
 }
 
@@ -362,9 +361,9 @@ __device__ __forceinline__ void st(T v, T *p, bool stream)
 // One pass over tile t: load, [phase], rotations, [E / adjoint terms / phase
 // undo], store.  The workgroup's sums of the E, <lam|X|phi> and <lam|C|phi>
 // terms are returned in sums[0..2] (valid in thread 0; zero when not taken).
-template <typename R, int MODE, bool TM>
+template <typename R, int MODE, bool TM, bool TM2 = TM>
 __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typename Tr<R>::V *lds,
-                                          double (&sums)[3])
+                                          double (&sums)[4])
 {
     using V = typename Tr<R>::V;
     using CT = typename Tr<R>::CT;
@@ -397,10 +396,13 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
     // before the final stores so that the workgroup retires right after issuing them.
 #define REDUCE()                                                                        \
     do {                                                                                \
-        if (wantE || wantB || wantG)                                                    \
-            block_sums3(accE, accB, accG, wantE, wantB, wantG, (double *)(lds + kLdsSlots), sums); \
-        else                                                                            \
-            sums[0] = sums[1] = sums[2] = 0.0;                                          \
+        if (wantE || wantB || wantG) {                                                  \
+            const double x_[4] = {accE, accB, accG, accB2};                             \
+            const bool w_[4] = {wantE, wantB, wantG, MODE == kBwdFuse};                 \
+            block_sums4(x_, w_, (double *)(lds + kLdsSlots), sums);                     \
+        } else {                                                                        \
+            sums[0] = sums[1] = sums[2] = sums[3] = 0.0;                                \
+        }                                                                               \
     } while (0)
 
     double accE = 0.0, accB = 0.0, accG = 0.0;
@@ -411,10 +413,11 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
     constexpr bool TURN = MODE == kTurn || MODE == kTurnPhase;
     // which optional steps this launch performs (compile-time where the mode decides)
     const bool phaseIn = MODE == kTurnPhase || (MODE == kFwd && (a.flags & kPhaseIn));
-    const bool phaseOut = MODE == kTurnPhase || (MODE == kBwd && (a.flags & kPhaseOut));
+    const bool phaseOut = MODE == kTurnPhase || MODE == kBwdFuse || (MODE == kBwd && (a.flags & kPhaseOut));
     const bool wantE = TURN || (MODE == kFwd && (a.flags & kEOut));
     const bool wantB = MODE != kFwd;
     const bool wantG = phaseOut;
+    double accB2 = 0.0;  // kBwdFuse: <lam|X|phi> terms of the second rotation's layer
     const bool costC = TURN || phaseOut || (MODE == kFwd && (a.flags & kEOut));
     CT cin[16], cv[16];
     if (phaseIn) {
@@ -577,14 +580,36 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                     l[r] = cmul(l[r], c, s);
                 }
         }
-        REDUCE();
-        if (!(a.flags & kNoStore)) {
+        if constexpr (MODE == kBwdFuse) {
+            // the same group's rotations of the previous layer, undone from C back to A
+            const R mb2 = (R)a.mul_b2;
+            const double f22 = a.fac_b2 * a.fac_b2;
+            double sig22 = 1.0;
+            adj_stage<2, TM2>(f, l, mb2, tmask, sig22, f22, accB2);
+            xpose<2, 1>(f, lds, lane, wave);
+            xpose<2, 1>(l, lds, lane, wave);
+            adj_stage<1, TM2>(f, l, mb2, tmask, sig22, f22, accB2);
+            xpose<1, 0>(f, lds, lane, wave);
+            xpose<1, 0>(l, lds, lane, wave);
+            adj_stage<0, TM2>(f, l, mb2, tmask, sig22, f22, accB2);
+            REDUCE();
+            const R sb2 = (R)a.scl_b2;
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                if (VC(r)) {
-                    st(f[r], &psi[ZC(r)], strm);
-                    st(l[r], &lam[ZC(r)], strm);
+                if (VA(r)) {
+                    st(vscale(f[r], sb2), &psi[ZA(r)], strm);
+                    st(vscale(l[r], sb2), &lam[ZA(r)], strm);
                 }
+        } else {
+            REDUCE();
+            if (!(a.flags & kNoStore)) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    if (VC(r)) {
+                        st(f[r], &psi[ZC(r)], strm);
+                        st(l[r], &lam[ZC(r)], strm);
+                    }
+            }
         }
     }
 #undef ZA
@@ -592,6 +617,62 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
 #undef VA
 #undef VC
 #undef REDUCE
+}
+
+// Layer-boundary forward pass on tile t: the group's rotations with layer l's
+// angle (arrangements A, B, C), layer l+1's phase (in C), the same group's
+// rotations with layer l+1's angle (C, B, A); loaded and stored in A.
+template <typename R, bool TM, bool TM2>
+__device__ __forceinline__ void tile_pass_fwd_fuse(const PassArgs &a, uint64_t t, typename Tr<R>::V *lds)
+{
+    using V = typename Tr<R>::V;
+    using CT = typename Tr<R>::CT;
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const Geometry &g = a.geo;
+    const uint64_t base = tile_base(t, g);
+    const bool full = g.tbits == (uint32_t)kTileBits;
+    const uint32_t lim = 1u << g.tbits;
+    const uint32_t tmask = g.tmask;
+    const bool strm = (a.flags & kStream) != 0;
+    V *psi = (V *)a.psi;
+    const CT *cost = (const CT *)a.cost;
+    const uint64_t thrA = base | dep(elem<0>(lane, wave, 0), g);
+    const uint64_t thrC = base | dep(elem<2>(lane, wave, 0), g);
+    const V zero = {(R)0, (R)0};
+    CT cv[16];
+    V v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        cv[r] = (full || elem<2>(lane, wave, r) < lim) ? ld(&cost[thrC | dep(elem<2>(0, 0, r), g)], strm) : (CT)0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        v[r] = (full || elem<0>(lane, wave, r) < lim) ? ld(&psi[thrA | dep(elem<0>(0, 0, r), g)], strm) : zero;
+    const R m1 = (R)a.mul_f, m2 = (R)a.mul_f2;
+    mix_stage<0, TM>(v, m1, tmask);
+    xpose<0, 1>(v, lds, lane, wave);
+    mix_stage<1, TM>(v, m1, tmask);
+    xpose<1, 2>(v, lds, lane, wave);
+    mix_stage<2, TM>(v, m1, tmask);
+    const R s1 = (R)a.scl_f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        R c, s;
+        phase_cs(-a.gamma_in, cv[r], c, s);
+        v[r] = cmul(vscale(v[r], s1), c, s);
+    }
+    mix_stage<2, TM2>(v, m2, tmask);
+    xpose<2, 1>(v, lds, lane, wave);
+    mix_stage<1, TM2>(v, m2, tmask);
+    xpose<1, 0>(v, lds, lane, wave);
+    mix_stage<0, TM2>(v, m2, tmask);
+    const R s2 = (R)a.scl_f2;
+    uint64_t thrS = thrA;  // see tile_pass_bwd_fuse
+    asm volatile("" : "+v"(thrS));
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (full || elem<0>(lane, wave, r) < lim) st(vscale(v[r], s2), &psi[thrS | dep(elem<0>(0, 0, r), g)], strm);
 }
 
 }  // namespace
