@@ -38,6 +38,11 @@ TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2407_13012_amd", "csrc", f)
                    for f in ("kernels.hip", "tile_device.h", "plan.cpp", "api.cpp", "qaoa_internal.h")]
 
 
+# template instance that runs each pass kind
+KERNEL_OF = {"forward": "k_pass<{}, kFwd>", "turn": "k_pass<{}, kTurn>", "backward": "k_pass<{}, kBwd>",
+             "boundary_forward": "k_pass_fuse<{}, kFwdFuse>", "boundary_backward": "k_pass_fuse<{}, kBwdFuse>"}
+
+
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -258,7 +263,7 @@ def main() -> int:
 
     kinds = {k: {"launches": v[0], "ms": v[1], "bytes": v[2],
                  "gbs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
-             for k, v in prof.items()}
+             for k, v in prof.items() if v[0] > 0}
     dom = max(kinds, key=lambda k: kinds[k]["ms"])
     dk = kinds[dom]
     achieved = dk["gbs"]
@@ -266,7 +271,7 @@ def main() -> int:
     kernel_ms = sum(v["ms"] for v in kinds.values()) / args.steps
     roofline = {
         "bound": "hbm",
-        "kernel": f"k_pass<{'double' if s == 16 else 'float'}, {dom}>",
+        "kernel": KERNEL_OF[dom].format("double" if s == 16 else "float"),
         "achieved": achieved,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
@@ -282,6 +287,7 @@ def main() -> int:
         "pass_time_ms_per_step": kernel_ms,
         "step_GBps": total_bytes / (ms_per_step * 1e-3) / 1e9,
         "model_bytes_per_amp": model_bytes_per_amp(args.n, p, s, c),
+        "implemented_bytes_per_amp": total_bytes / N,
         "model_roofline_frac": model_bytes_per_amp(args.n, p, s, c) * N / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "create_s": t_create,
     }
@@ -318,7 +324,7 @@ def main() -> int:
                         "E": E64, "E_rel_diff_vs_c128": abs(E64 - E) / max(abs(E), 1.0),
                         "passes": {k: {"launches": v[0], "ms": v[1], "bytes": v[2],
                                        "gbs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
-                                   for k, v in prof64.items()}}
+                                   for k, v in prof64.items() if v[0] > 0}}
         print(f"[bench] c64 {extra['c64']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
 
     if not args.no_batch:

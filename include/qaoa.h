@@ -216,7 +216,8 @@ qaoa_status qaoa_optimize(qaoa_handle h, int32_t p, double *gamma, double *beta,
  * qaoa_gradient) is bracketed by a pair of HIP events on the handle's stream.
  * qaoa_profile_enable (re)starts the counters (on != 0) or stops timing
  * (on == 0).  qaoa_profile_read synchronises the stream and reports, for one
- * pass kind (0 forward, 1 turn, 2 backward), the number of launches, their
+ * pass kind (0 forward, 1 turn, 2 backward, 3 layer-boundary forward, 4
+ * layer-boundary backward), the number of launches, their
  * summed GPU time in milliseconds and their summed algorithmic bytes (each
  * amplitude vector read or written once, plus one cost-diagonal read where the
  * pass applies or measures C).  Any output pointer may be NULL.

@@ -486,7 +486,7 @@ def qaoa_mpnn_train_step(m, graphs, gamma_t, beta_t, p: int, lr=1e-3, beta1=0.9,
     return loss.value
 
 
-PASS_KINDS = ("forward", "turn", "backward")
+PASS_KINDS = ("forward", "turn", "backward", "boundary_forward", "boundary_backward")
 
 
 def qaoa_profile_enable(h, on: bool = True) -> None:
@@ -494,7 +494,7 @@ def qaoa_profile_enable(h, on: bool = True) -> None:
 
 
 def qaoa_profile_read(h, kind: int):
-    """Return (launches, total_ms, total_algorithmic_bytes) for pass kind 0/1/2."""
+    """Return (launches, total_ms, total_algorithmic_bytes) for one pass kind (index into PASS_KINDS)."""
     n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
     _check(load_library().qaoa_profile_read(h, int(kind), ctypes.byref(n), ctypes.byref(ms),
                                             ctypes.byref(by)), "qaoa_profile_read")
@@ -633,7 +633,7 @@ class QaoaHandle:
         qaoa_profile_enable(self._h, on)
 
     def profile_read(self):
-        """{kind: (launches, ms, bytes)} for the forward, turn and backward passes."""
+        """{kind: (launches, ms, bytes)} for every pass kind in PASS_KINDS."""
         return {k: qaoa_profile_read(self._h, i) for i, k in enumerate(PASS_KINDS)}
 
 

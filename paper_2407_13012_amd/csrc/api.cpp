@@ -66,9 +66,10 @@ struct qaoa_handle_s {
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> event_pool;
-    int64_t prof_launches[3] = {0, 0, 0};
-    double prof_ms[3] = {0, 0, 0};
-    double prof_bytes[3] = {0, 0, 0};
+    // per pass kind: forward, turn, backward, layer-boundary forward, layer-boundary backward
+    int64_t prof_launches[5] = {0, 0, 0, 0, 0};
+    double prof_ms[5] = {0, 0, 0, 0, 0};
+    double prof_bytes[5] = {0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -302,9 +303,9 @@ qaoa_status run_pass(qaoa_handle h, int mode, const qk::PassArgs &a)
         HIPCHECK(h, qk::launch_pass(mode, c64(h), a, nblocks(h->n), h->stream));
         return QAOA_OK;
     }
-    // reported kinds: forward (also layer-boundary forward), turn, backward
-    const int kind = (mode == qk::kFwd || mode == qk::kFwdFuse) ? 0
-                     : (mode == qk::kTurn || mode == qk::kTurnPhase) ? 1 : 2;
+    // reported kinds: 0 forward, 1 turn, 2 backward, 3 / 4 layer-boundary forward / backward
+    const int kind = mode == qk::kFwd ? 0 : (mode == qk::kTurn || mode == qk::kTurnPhase) ? 1
+                     : mode == qk::kBwd ? 2 : mode == qk::kFwdFuse ? 3 : 4;
     qaoa_handle_s::Pending pd{kind, pass_bytes(h, mode, a), nullptr, nullptr};
     qaoa_status st = take_event(h, &pd.t0);
     if (st == QAOA_OK) st = take_event(h, &pd.t1);
@@ -837,7 +838,7 @@ qaoa_status qaoa_profile_enable(qaoa_handle h, int32_t on)
     DeviceGuard dg(h->device);
     if ((st = drain_profile(h)) != QAOA_OK) return st;
     h->profiling = on != 0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 5; ++k) {
         h->prof_launches[k] = 0;
         h->prof_ms[k] = 0;
         h->prof_bytes[k] = 0;
@@ -850,7 +851,7 @@ qaoa_status qaoa_profile_read(qaoa_handle h, int32_t kind, int64_t *launches, do
 {
     qaoa_status st = check_handle(h);
     if (st != QAOA_OK) return st;
-    if (kind < 0 || kind > 2) return fail(QAOA_ERR_INVALID_ARGUMENT, "kind must be 0, 1 or 2");
+    if (kind < 0 || kind > 4) return fail(QAOA_ERR_INVALID_ARGUMENT, "kind must be in [0, 4]");
     DeviceGuard dg(h->device);
     if ((st = drain_profile(h)) != QAOA_OK) return st;
     if (launches) *launches = h->prof_launches[kind];
