@@ -98,6 +98,56 @@ def time_gradients(q, gamma, beta, steps, warmup):
     return t1 - t0, prof
 
 
+def copy_ceiling(gib: float) -> float:
+    """Practical HBM ceiling: GB/s (bytes read + written) of a plain device copy."""
+    import torch
+    nel = int(gib * (1 << 30)) // 8
+    x = torch.empty(nel, dtype=torch.float64, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * nel * 8 / dt / 1e9
+
+
+def small_workloads() -> dict:
+    """The two smaller configurations: E+G latency of the n=12, p=2 MaxCut and
+    E+G time of the n=26 3-regular weighted MaxCut (p=6) in both precisions,
+    the latter against its byte model (P_min = 2)."""
+    import torch
+
+    import qaoa_inputs as qi
+    from paper_2407_13012_amd import QaoaHandle
+    out = {}
+    w = qi.workload_small()
+    with QaoaHandle.from_instance(w["instance"]) as q:
+        for _ in range(5):
+            q.gradient(w["gamma"], w["beta"])
+        t0 = time.perf_counter()
+        for _ in range(100):
+            q.gradient(w["gamma"], w["beta"])
+        out["maxcut12_p2_grad_us"] = (time.perf_counter() - t0) / 100 * 1e6
+    w = qi.workload_regular26()
+    for prec, s, c in (("c128", 16, 8), ("c64", 8, 4)):
+        with QaoaHandle.from_instance(w["instance"], prec) as q:
+            q.gradient(w["gamma"], w["beta"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                q.gradient(w["gamma"], w["beta"])
+            dt = (time.perf_counter() - t0) / 10
+        out[f"regular26_p6_{prec}_grad_ms"] = dt * 1e3
+        out[f"regular26_p6_{prec}_model_roofline_frac"] = (model_bytes_per_amp(26, 6, s, c) * 2.0 ** 26 / dt
+                                                           / (HBM_PEAK_GBS * 1e9))
+    return out
+
+
 def batch_bytes_per_amp(n: int, p: int, kmax: int = 10) -> float:
     """Algorithmic bytes per amplitude of one batched-engine E+G (complex128, fp64 C):
     p layers forward (P passes each moving psi, one also reading C), one sweep
@@ -245,6 +295,11 @@ def main() -> int:
         del x, y
         torch.cuda.empty_cache()
 
+    copy_gbs = None
+    if not args.no_extras:
+        copy_gbs = copy_ceiling(8.0)
+        print(f"[bench] device copy 8 GiB: {copy_gbs:.0f} GB/s (read + write)", file=sys.stderr, flush=True)
+
     w = qi.workload_qubo32(args.n)
     inst, gamma, beta = w["instance"], w["gamma"], w["beta"]
     p = len(gamma)
@@ -289,6 +344,9 @@ def main() -> int:
         "model_bytes_per_amp": model_bytes_per_amp(args.n, p, s, c),
         "implemented_bytes_per_amp": total_bytes / N,
         "model_roofline_frac": model_bytes_per_amp(args.n, p, s, c) * N / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        # the same step against one sweep per layer (312 B/amp at c128): the ideal a single-pass mixer would need
+        "ideal_p1_roofline_frac": (p * (6 * s + 2 * c) + c - 2 * s) * N / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "copy_GBps": copy_gbs,
         "create_s": t_create,
     }
     E, dg, db = q.gradient(gamma, beta)
@@ -326,6 +384,12 @@ def main() -> int:
                                        "gbs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
                                    for k, v in prof64.items() if v[0] > 0}}
         print(f"[bench] c64 {extra['c64']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+
+    if not args.no_extras:
+        extra.update(small_workloads())
+        print(f"[bench] n=12 E+G {extra['maxcut12_p2_grad_us']:.0f} us; n=26 p=6 E+G "
+              f"{extra['regular26_p6_c128_grad_ms']:.1f} ms (c128), {extra['regular26_p6_c64_grad_ms']:.1f} ms (c64)",
+              file=sys.stderr, flush=True)
 
     if not args.no_batch:
         extra["batch"] = batch_leg(args.batch_graphs, 4, args.batch_steps,
