@@ -137,6 +137,65 @@ __device__ __forceinline__ void run_tiles(const PassArgs &a, uint64_t T, double2
     __syncthreads();  // this pass's stores are visible to the next pass
 }
 
+// Second rotation of a layer-boundary pass (the other layer's angle).
+__device__ __forceinline__ void make_second(PassArgs &a, double beta2)
+{
+    double s, c;
+    sincos(beta2, &s, &c);
+    const int k = __builtin_popcount(a.geo.tmask);
+    const bool tm = fabs(c) >= fabs(s);
+    const double mf = tm ? s / c : c / s, ff = tm ? c : s, fb = tm ? c : -s;
+    double sf = 1.0, sb = 1.0;
+    for (int i = 0; i < k; ++i) {
+        sf *= ff;
+        sb *= fb;
+    }
+    a.tan_mode2 = uni(tm ? 1u : 0u);
+    a.mul_f2 = uni(mf);
+    a.mul_b2 = -a.mul_f2;
+    a.fac_b2 = uni(fb);
+    a.scl_f2 = uni(sf);
+    a.scl_b2 = uni(sb);
+}
+
+// All tiles of one layer-boundary pass; for kBwdFuse acc gets the X terms of
+// the later layer ([1]), the C term ([2]) and the X terms of the earlier layer ([3]).
+template <int MODE>
+__device__ __forceinline__ void run_tiles_fuse(const PassArgs &a, uint64_t T, double2 *lds, double (&acc)[4])
+{
+    for (uint64_t t = 0; t < T; ++t) {
+        PassArgs b = a;
+#pragma unroll
+        for (int r = 0; r < kTileRuns; ++r) {
+            opaque(b.geo.t_src[r]);
+            opaque(b.geo.t_dst[r]);
+            opaque(b.geo.t_len[r]);
+        }
+        opaque(b.geo.tmask);
+        opaque(b.geo.tbits);
+        const int sel = (b.tan_mode ? 2 : 0) + (b.tan_mode2 ? 1 : 0);
+        if constexpr (MODE == kFwdFuse) {
+            if (sel == 3) tile_pass_fwd_fuse<double, true, true>(b, t, lds);
+            else if (sel == 2) tile_pass_fwd_fuse<double, true, false>(b, t, lds);
+            else if (sel == 1) tile_pass_fwd_fuse<double, false, true>(b, t, lds);
+            else tile_pass_fwd_fuse<double, false, false>(b, t, lds);
+        } else {
+            double s[4];
+            if (sel == 3) tile_pass<double, kBwdFuse, true, true>(b, t, lds, s);
+            else if (sel == 2) tile_pass<double, kBwdFuse, true, false>(b, t, lds, s);
+            else if (sel == 1) tile_pass<double, kBwdFuse, false, true>(b, t, lds, s);
+            else tile_pass<double, kBwdFuse, false, false>(b, t, lds, s);
+            acc[1] += s[1];
+            acc[2] += s[2];
+            acc[3] += s[3];
+        }
+    }
+    __syncthreads();
+}
+
+// Mixer group at position idx of layer l (even layers ascending, odd descending).
+__device__ __forceinline__ int group_at(int l, int idx, int P) { return (l % 2 == 0) ? idx : P - 1 - idx; }
+
 // E (out[0]) and, with grad, dE/dgamma (out[1 .. p]) and dE/dbeta (out[p+1 ..])
 // of the instance in the workgroup's slot; th = (gamma, beta).  out is shared
 // memory written by thread 0.  Schedule (Sec. II-B / IV-C): the p layers
@@ -152,10 +211,22 @@ __device__ __forceinline__ void wg_eval(const BatchArgs &B, int n, bool grad, co
     const uint64_t T = n > kTileBits ? 1ull << (n - kTileBits) : 1ull;
     const uint32_t tid = threadIdx.x;
     PassArgs a;
+    // Layers visit their mixer groups in alternating order, so that with two or
+    // more groups per layer the groups meeting at a layer boundary share one
+    // sweep (the single-instance schedule, without the turn pass).
     for (int l = 0; l < p; ++l) {
-        for (int gi = 0; gi < P; ++gi) {
+        for (int idx = 0; idx < P; ++idx) {
+            if (P > 1 && l > 0 && idx == 0) continue;
+            const int gi = P > 1 ? group_at(l, idx, P) : 0;
             make_args(a, B, n, gi, uni(th[p + l]), psi, lam, cost);
-            if (gi == 0) {
+            if (P > 1 && idx == P - 1 && l < p - 1) {
+                make_second(a, uni(th[p + l + 1]));
+                a.gamma_in = uni(th[l + 1]);
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                run_tiles_fuse<kFwdFuse>(a, T, lds, acc);
+                continue;
+            }
+            if (idx == 0) {
                 a.flags |= kPhaseIn;
                 a.gamma_in = uni(th[l]);
                 if (l == 0) a.flags |= kInit;
@@ -180,9 +251,24 @@ __device__ __forceinline__ void wg_eval(const BatchArgs &B, int n, bool grad, co
     if (!grad) return;
     __syncthreads();  // lam stores visible to the passes
     for (int l = p - 1; l >= 0; --l) {
-        for (int gi = P - 1; gi >= 0; --gi) {
+        for (int j = 0; j < P; ++j) {
+            const int idx = P - 1 - j;
+            if (P > 1 && j == 0 && l < p - 1) continue;  // done with layer l + 1's boundary sweep
+            const int gi = P > 1 ? group_at(l, idx, P) : 0;
             make_args(a, B, n, gi, uni(th[p + l]), psi, lam, cost);
-            if (gi == 0) {
+            if (P > 1 && idx == 0 && l > 0) {
+                make_second(a, uni(th[p + l - 1]));
+                a.gamma_out = uni(th[l]);
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                run_tiles_fuse<kBwdFuse>(a, T, lds, acc);
+                if (tid == 0) {
+                    out[1 + p + l] += acc[1];
+                    out[1 + l] += acc[2];
+                    out[p + l] += acc[3];
+                }
+                continue;
+            }
+            if (idx == 0) {
                 a.flags |= kPhaseOut;
                 a.gamma_out = uni(th[l]);
                 if (l == 0) a.flags |= kNoStore;
