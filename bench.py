@@ -433,6 +433,12 @@ def main() -> int:
             "state_bytes": int(N * s), "precision": args.precision,
         },
         "roofline": roofline,
+        # whole E+G against the byte model of the survey (p(6 P s + 2c) + c - 2s per
+        # amplitude with P = ceil(n / kmax)): the roofline figure the target refers to
+        "step_roofline": {"bound": "hbm", "model_bytes_per_amp": extra["model_bytes_per_amp"],
+                          "implemented_bytes_per_amp": extra["implemented_bytes_per_amp"],
+                          "achieved": extra["model_bytes_per_amp"] * N / (ms_per_step * 1e-3) / 1e9,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": extra["model_roofline_frac"]},
         "cpu_baseline": cpu,
         "extra": extra,
     }
