@@ -81,6 +81,7 @@ def train(graphs, gamma, beta, p: int, epochs: int = 30, batch: int = 256, lr: f
         vg = [graphs[i] for i in val]
         base, _ = m.loss_grad(vg, gamma[val], beta[val], want_grad=False)
         hist.append({"epoch": 0, "val_loss": base})
+        best_val, best_params, best_epoch = base, m.get_params(), 0
         t0 = time.perf_counter()
         for ep in range(1, epochs + 1):
             rng.shuffle(tr)
@@ -92,11 +93,13 @@ def train(graphs, gamma, beta, p: int, epochs: int = 30, batch: int = 256, lr: f
                 losses.append(m.train_step([graphs[i] for i in idx], gamma[idx], beta[idx], lr=lr_ep))
             vl, _ = m.loss_grad(vg, gamma[val], beta[val], want_grad=False)
             hist.append({"epoch": ep, "train_loss": float(np.mean(losses)), "val_loss": vl})
+            if vl < best_val:  # keep the parameters with the lowest validation loss
+                best_val, best_params, best_epoch = vl, m.get_params(), ep
             if ep % log_every == 0 or ep == epochs:
                 log(f"[warmstart] epoch {ep}: train {np.mean(losses):.3e} val {vl:.3e}")
         secs = time.perf_counter() - t0
-        params = m.get_params()
-    return params, {"history": hist, "train_seconds": secs, "train_graphs": int(len(tr)), "val_graphs": int(nval)}
+    return best_params, {"history": hist, "train_seconds": secs, "train_graphs": int(len(tr)),
+                         "val_graphs": int(nval), "best_epoch": best_epoch, "best_val_loss": best_val}
 
 
 def _lbfgs_counted(h: QaoaHandle, x0, p: int, max_iter: int, gtol: float):
@@ -175,7 +178,7 @@ def evaluate(params, graphs, p: int, tol: float = 0.005, max_iter: int = 200, gt
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--out", default="warmstart_out")
-    ap.add_argument("--train-graphs", type=int, default=4096)
+    ap.add_argument("--train-graphs", type=int, default=12288)
     ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--epochs", type=int, default=300)
