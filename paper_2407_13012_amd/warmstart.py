@@ -67,8 +67,11 @@ def build_dataset(graphs, p: int, steps: int, tuned: bool = True, log=print) -> 
 
 
 def train(graphs, gamma, beta, p: int, epochs: int = 30, batch: int = 256, lr: float = 2e-3,
-          seed: int = 0, val_frac: float = 0.1, theta0=None, log=print, log_every: int = 1):
-    """Fit the network to (graphs -> gamma, beta).  Returns (params, history)."""
+          seed: int = 0, val_frac: float = 0.1, theta0=None, log=print, log_every: int = 1,
+          select: str = "last"):
+    """Fit the network to (graphs -> gamma, beta).  Returns (params, history): the
+    parameters after the last epoch, or with select="best" those of the epoch
+    with the lowest validation loss."""
     from qaoa_inputs import mpnn_init_params  # seeded initial weights (inputs, no network arithmetic)
     rng = np.random.default_rng(seed)
     G = len(graphs)
@@ -98,8 +101,10 @@ def train(graphs, gamma, beta, p: int, epochs: int = 30, batch: int = 256, lr: f
             if ep % log_every == 0 or ep == epochs:
                 log(f"[warmstart] epoch {ep}: train {np.mean(losses):.3e} val {vl:.3e}")
         secs = time.perf_counter() - t0
-    return best_params, {"history": hist, "train_seconds": secs, "train_graphs": int(len(tr)),
-                         "val_graphs": int(nval), "best_epoch": best_epoch, "best_val_loss": best_val}
+        last_params = m.get_params()
+    return (best_params if select == "best" else last_params), {
+        "history": hist, "train_seconds": secs, "train_graphs": int(len(tr)), "val_graphs": int(nval),
+        "best_epoch": best_epoch, "best_val_loss": best_val, "selected": select}
 
 
 def _lbfgs_counted(h: QaoaHandle, x0, p: int, max_iter: int, gtol: float):
@@ -178,7 +183,8 @@ def evaluate(params, graphs, p: int, tol: float = 0.005, max_iter: int = 200, gt
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--out", default="warmstart_out")
-    ap.add_argument("--train-graphs", type=int, default=12288)
+    ap.add_argument("--train-graphs", type=int, default=4096)
+    ap.add_argument("--select", choices=["last", "best"], default="last")
     ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--epochs", type=int, default=300)
@@ -200,23 +206,24 @@ def main(argv=None) -> int:
     save_dataset(os.path.join(args.out, f"dataset_p{args.p}.npz"), graphs, args.p, ds["gamma"], ds["beta"],
                  ds["e_first"], ds["e_last"], ds["cmax"],
                  meta={"adam_steps": args.train_steps, "engine_seconds": ds["seconds"]})
-    log(f"[warmstart] dataset median ratio {np.median(ds['e_last'] / ds['cmax']):.4f} "
-        f"(start {np.median(ds['e_first'] / ds['cmax']):.4f})")
+    cm = np.maximum(ds["cmax"], 1e-9)
+    log(f"[warmstart] dataset median ratio {np.median(ds['e_last'] / cm):.4f} "
+        f"(start {np.median(ds['e_first'] / cm):.4f})")
     # graphs whose optimisation stayed poor (tiny max C, or a run that did not
     # reach min_ratio) carry little information about good angles
-    ratio = np.where(ds["cmax"] > 1e-9, ds["e_last"] / np.maximum(ds["cmax"], 1e-9), 0.0)
+    ratio = ds["e_last"] / np.maximum(ds["cmax"], 1e-9)
     keep = np.nonzero(ratio >= args.min_ratio)[0]
     log(f"[warmstart] training on {keep.size} of {len(graphs)} graphs (final ratio >= {args.min_ratio})")
     params, info = train([graphs[i] for i in keep], ds["gamma"][keep], ds["beta"][keep], args.p,
                          epochs=args.epochs, batch=args.batch, lr=args.lr, log=log,
-                         log_every=max(1, args.epochs // 20))
+                         log_every=max(1, args.epochs // 20), select=args.select)
     np.save(os.path.join(args.out, f"mpnn_p{args.p}.npy"), params)
     ev_graphs = qi.warmstart_eval_graphs(args.eval_graphs, args.eval_n)
     res = evaluate(params, ev_graphs, args.p, max_iter=args.max_iter, log=log)
     res["training"] = info
     res["dataset"] = {"graphs": len(graphs), "adam_steps": args.train_steps, "engine_seconds": ds["seconds"],
-                      "median_ratio_start": float(np.median(ds["e_first"] / ds["cmax"])),
-                      "median_ratio_final": float(np.median(ds["e_last"] / ds["cmax"])),
+                      "median_ratio_start": float(np.median(ds["e_first"] / np.maximum(ds["cmax"], 1e-9))),
+                      "median_ratio_final": float(np.median(ds["e_last"] / np.maximum(ds["cmax"], 1e-9))),
                       "training_graphs_kept": int(keep.size)}
     with open(os.path.join(args.out, "warmstart_eval.json"), "w") as fh:
         json.dump(res, fh, indent=1)
