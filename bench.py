@@ -248,6 +248,17 @@ def cpu_baseline(inst_fn, p_n, full_n, gamma, beta, batch_sample: int = 64):
         "sample": (f"one oracle E+G ({dt:.2f} s) of the n={p_n} member of the same QUBO family "
                    f"(p={len(gamma)}), scaled by 2^{full_n - p_n} to n={full_n} (extrapolated)"),
     }
+    # the two smaller configurations, timed in full: MaxCut ER(12, 0.5) at p = 2 and the
+    # n = 26 weighted 3-regular MaxCut at p = 6 (complex128)
+    for key, wl in (("maxcut12_p2", qi.workload_small), ("regular26_p6", qi.workload_regular26)):
+        w = wl()
+        g = w["instance"]
+        Cw = oracle.cost_of(g)
+        reps = 20 if g.n <= 12 else 1
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            oracle.gradient(g.n, Cw, w["gamma"], w["beta"])
+        out[key + "_grad_s"] = (time.perf_counter() - t0) / reps
     if batch_sample:
         # batched-engine workload: every 64th graph of the 4096-graph family, p = 4, one E+G each
         graphs = qi.batched_family(4096)[::4096 // batch_sample]
