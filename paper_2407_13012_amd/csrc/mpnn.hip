@@ -488,6 +488,10 @@ qaoa_status ensure_ws(qaoa_mpnn m, int G, int N, int E2)
         (void)hipFree(m->ws);
         m->ws = nullptr;
         fr += m->ws_bytes;
+        // no workspace until the new one is carved: a failed allocation below
+        // must not leave the old capacities pointing at freed memory
+        m->ws_bytes = 0;
+        m->ws_graphs = m->ws_nodes = m->ws_edges = 0;
     }
     if (total > fr) return mfail(QAOA_ERR_OUT_OF_MEMORY, "workspace does not fit in device memory");
     MCHECK(m, hipMalloc(&m->ws, total));
