@@ -164,7 +164,8 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
  *   z     uint64 [shots] receiving basis indices
  *   cost  fp64 [shots] receiving C[z], or NULL
  *   out_is_device  nonzero if z / cost are device memory
- * Errors: NO_STATE; INVALID_ARGUMENT for shots < 0 or a zero-norm state.
+ * Errors: NO_STATE; INVALID_ARGUMENT for shots outside [0, 2^40] or a zero-norm
+ * state; OUT_OF_MEMORY when host outputs need more device staging than is free.
  */
 qaoa_status qaoa_sample(qaoa_handle h, int64_t shots, uint64_t seed, uint64_t *z, double *cost,
                         int32_t out_is_device);

@@ -796,6 +796,8 @@ qaoa_status qaoa_sample(qaoa_handle h, int64_t shots, uint64_t seed, uint64_t *z
     qaoa_status st = check_handle(h);
     if (st != QAOA_OK) return st;
     if (shots < 0) return fail(QAOA_ERR_INVALID_ARGUMENT, "shots must be >= 0");
+    // bounds the staging arithmetic below far from overflow (2^40 shots = 16 TiB of output)
+    if (shots > ((int64_t)1 << 40)) return fail(QAOA_ERR_INVALID_ARGUMENT, "shots must be <= 2^40");
     if (shots > 0 && !z) return fail(QAOA_ERR_INVALID_ARGUMENT, "z is NULL");
     if (!h->state_valid) return fail(QAOA_ERR_NO_STATE, "no current state");
     if (shots == 0) return QAOA_OK;

@@ -275,6 +275,11 @@ def test_sample_errors():
         q.statevector([0.1], [0.2], copy=False)
         with pytest.raises(QaoaError):
             q.sample(-1, 1)
+        import torch
+        t = torch.empty(1, dtype=torch.int64, device="cuda")
+        with pytest.raises(QaoaError) as ei:
+            q.sample(2**41, 1, z_out=t)  # rejected before anything is written
+        assert ei.value.status == 1
         z, c = q.sample(0, 1)
         assert z.size == 0
 
