@@ -184,3 +184,32 @@ def test_batch_family_sampled_full_run():
         np.testing.assert_allclose(gam[i], og, rtol=0, atol=1e-6, err_msg=f"n={g.n}")
         np.testing.assert_allclose(bet[i], ob, rtol=0, atol=1e-6, err_msg=f"n={g.n}")
         assert abs(e1[i] - oe1) <= 1e-7 * max(1.0, float(np.abs(g.weight_array()).sum()))
+
+
+def test_batch_matches_single_instance_library():
+    """The batched engine's Adam trajectory equals Adam driven from the host by
+    the single-instance library's gradients (same updates, gradients agreeing to
+    rounding)."""
+    from paper_2407_13012_amd import QaoaHandle
+    graphs = family([11, 15, 19], seed=71)
+    p, steps = 3, 3
+    g0, b0 = start_angles(graphs, p, seed=3)
+    gam, bet, e0, e1 = run_batch(graphs, p, g0, b0, steps=steps)
+    for i, g in enumerate(graphs):
+        sc = scale_of(g)
+        x = np.concatenate([g0[i], b0[i]])
+        m = np.zeros_like(x)
+        v = np.zeros_like(x)
+        with QaoaHandle.from_instance(g) as q:
+            E_first = None
+            for t in range(1, steps + 1):
+                E, dg, db = q.gradient(x[:p], x[p:])
+                E_first = E if E_first is None else E_first
+                gr = sc * np.concatenate([dg, db])
+                m = 0.9 * m + 0.1 * gr
+                v = 0.999 * v + 0.001 * gr * gr
+                x = x + 0.05 * (m / (1 - 0.9 ** t)) / (np.sqrt(v / (1 - 0.999 ** t)) + 1e-8)
+            E_last = q.evaluate(x[:p], x[p:])
+        np.testing.assert_allclose(np.r_[gam[i], bet[i]], x, rtol=0, atol=1e-9)
+        assert abs(e0[i] - E_first) <= 1e-10 * max(1.0, 1.0 / sc)
+        assert abs(e1[i] - E_last) <= 1e-9 * max(1.0, 1.0 / sc)
