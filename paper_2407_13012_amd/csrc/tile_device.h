@@ -286,6 +286,16 @@ __device__ __forceinline__ double upow(double f, int k)
     return r;
 }
 
+// Workgroup barrier ordering LDS accesses only: a wave waits for its own LDS
+// operations, not for its outstanding global loads and stores, so a tile's
+// transposes do not stall on memory traffic that they do not depend on.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int FROM, int TO, typename V>
 __device__ __forceinline__ void xpose(V (&v)[16], V *lds, uint32_t lane, uint32_t wave)
 {
@@ -293,10 +303,10 @@ __device__ __forceinline__ void xpose(V (&v)[16], V *lds, uint32_t lane, uint32_
     V *rd = lds + lds_slot(elem<TO>(lane, wave, 0));
 #pragma unroll
     for (int r = 0; r < 16; ++r) wr[lds_slot(elem<FROM>(0, 0, r))] = v[r];
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = rd[lds_slot(elem<TO>(0, 0, r))];
-    __syncthreads();
+    lds_barrier();
 }
 
 __device__ __forceinline__ double wave_sum(double x)
@@ -335,7 +345,7 @@ __device__ __forceinline__ void block_sums4(const double (&x)[4], const bool (&w
 #pragma unroll
         for (int k = 0; k < 4; ++k) red[4 * k + wave] = w[k];
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         out[k] = 0.0;
@@ -498,7 +508,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                     const V *rd = lds + lds_slot(elem<1>(lane, wave, 0));
 #pragma unroll
                     for (int r = 0; r < 16; ++r) v[r] = rd[lds_slot(elem<1>(0, 0, r))];
-                    __syncthreads();
+                    lds_barrier();
                 }
                 xpose<2, 1>(l, lds, lane, wave);
                 // lam misses fb^kC, phi (forward stages A, B) misses ff^(kA+kB)
