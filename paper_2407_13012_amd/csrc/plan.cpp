@@ -9,7 +9,8 @@
 //   * pass 0 rotates a contiguous run of low bits [0, 12 - x0) plus x0 high
 //     bits, so its global accesses are runs of >= 64 consecutive amplitudes;
 //   * passes 1.. keep the S = 12 - k lowest bits as non-rotated spectators
-//     (runs of 2^S consecutive amplitudes) and rotate k <= 10 further bits;
+//     (runs of 2^S consecutive amplitudes) and rotate k <= 10 further bits
+//     (k <= 9 for 8-byte amplitudes, so that runs stay >= 64 bytes);
 //   * bits whose stride spans a 2 MiB page (bit >= 17 for 16-byte amplitudes,
 //     >= 18 for 8-byte ones) are spread evenly over the passes, since every
 //     such target bit doubles the number of pages one tile touches.
@@ -77,6 +78,8 @@ std::vector<PassPlan> plan_passes(int n, bool c64, int kmax)
     if (n <= kTileBits) return {{low_mask(n), low_mask(n)}};
     if (kmax < 1) kmax = 1;
     if (kmax > 10) kmax = 10;
+    // 8-byte amplitudes: keep >= 3 spectator bits (runs of >= 64 B) in the later passes
+    if (c64 && kmax > 9) kmax = 9;
     const int page = c64 ? 18 : 17;
     const int r = n - kTileBits, P1 = (r + kmax - 1) / kmax;
     std::vector<int> k(P1 + 1), x(P1 + 1, 0), cap(P1 + 1);

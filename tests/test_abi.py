@@ -158,9 +158,12 @@ def test_pass_plan_invariants(prec):
             if i == 0:
                 assert tgt & 63 == min(63, (1 << n) - 1)
             elif n > 12:
-                assert spect >= 3  # at least 2 spectator bits (>= 4 consecutive amplitudes)
+                # at least 2 spectator bits (>= 4 consecutive amplitudes, 64 B at complex128),
+                # at least 3 at complex64 (again >= 64 B)
+                assert spect >= (3 if prec == "c128" else 7)
         assert seen == (1 << n) - 1
-        assert len(plan) == (1 if n <= 12 else 1 + -(-(n - 12) // 10))
+        kmax = 10 if prec == "c128" else 9  # 8-byte amplitudes keep >= 3 spectator bits
+        assert len(plan) == (1 if n <= 12 else 1 + -(-(n - 12) // kmax))
         # page-crossing qubits are spread evenly
         X = max(0, n - page)
         if X:
