@@ -136,6 +136,12 @@ __device__ __forceinline__ double imcx(V u, V v)
 {
     return (double)u.x * (double)v.y - (double)u.y * (double)v.x;
 }
+// acc + Im(conj(u) v) as two chained FMAs.
+template <typename V>
+__device__ __forceinline__ double imcx_acc(V u, V v, double acc)
+{
+    return fma(-(double)u.y, (double)v.x, fma((double)u.x, (double)v.y, acc));
+}
 
 // sin and cos of x in fp64.  Cody-Waite reduction x = k pi/2 + r with pi/2
 // split into two 33-bit parts and a remainder (k pi/2 is exact for |k| < 2^20),
@@ -242,7 +248,7 @@ __device__ __forceinline__ void adj_stage(V (&f)[16], V (&l)[16], R m, uint32_t 
             for (int r = 0; r < 16; ++r)
                 if (!(r & (1 << q))) {
                     const int r1 = r | (1 << q);
-                    ps += imcx(l[r], f[r1]) + imcx(l[r1], f[r]);
+                    ps = imcx_acc(l[r1], f[r], imcx_acc(l[r], f[r1], ps));
                 }
             accB = fma(sig2, ps, accB);
             sig2 *= f2;
@@ -270,7 +276,7 @@ __device__ __forceinline__ void beta_terms(const V (&f)[16], const V (&l)[16], u
             for (int r = 0; r < 16; ++r)
                 if (!(r & (1 << q))) {
                     const int r1 = r | (1 << q);
-                    ps += imcx(l[r], f[r1]) + imcx(l[r1], f[r]);
+                    ps = imcx_acc(l[r1], f[r], imcx_acc(l[r], f[r1], ps));
                 }
         }
     }
