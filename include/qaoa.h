@@ -231,9 +231,10 @@ qaoa_status qaoa_profile_read(qaoa_handle h, int32_t kind, int64_t *launches, do
  * Pass plan of one mixer layer (host-side introspection; no GPU is touched).
  * The n rotations exp(-i b X_j) of a layer commute (Eq. (1)), so the library
  * applies them in a few sweeps over the state.  In sweep i one workgroup owns
- * the 2^min(n,12) amplitudes whose indices differ only in the bits of
- * tile_bits[i] and rotates the qubits in target_bits[i]; the remaining tile
- * bits are low spectator bits kept for contiguous memory access.
+ * the 2^min(n,TB) amplitudes whose indices differ only in the bits of
+ * tile_bits[i] (TB = 12 for QAOA_C128, 13 for QAOA_C64: 64 KiB of state) and
+ * rotates the qubits in target_bits[i]; the remaining tile bits are low
+ * spectator bits kept for contiguous memory access (runs of >= 64 bytes).
  *   cap       capacity of the two output arrays
  *   npasses   receives the number of sweeps per layer
  * Errors: INVALID_ARGUMENT for n outside [1, QAOA_MAX_QUBITS], an unknown

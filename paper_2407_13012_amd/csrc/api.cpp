@@ -135,7 +135,13 @@ qaoa_status device_fail(qaoa_handle h, const char *what, hipError_t e)
 inline size_t amp_bytes(int prec) { return prec == QAOA_C64 ? 8 : 16; }
 inline size_t cost_bytes(int prec) { return prec == QAOA_C64 ? 4 : 8; }
 inline bool c64(const qaoa_handle h) { return h->prec == QAOA_C64; }
-inline uint64_t nblocks(int n) { return n <= qk::kTileBits ? 1ull : (1ull << (n - qk::kTileBits)); }
+// Workgroups (tiles) of a pass kernel launch.
+inline uint64_t nblocks(int n, bool c64)
+{
+    const int tb = qk::tile_bits(c64);
+    return n <= tb ? 1ull : (1ull << (n - tb));
+}
+inline uint64_t nblocks(const qaoa_handle h) { return nblocks(h->n, c64(h)); }
 
 qaoa_status check_handle(qaoa_handle h)
 {
@@ -209,7 +215,7 @@ qk::PassArgs pass_args(qaoa_handle h, const qk::PassPlan &pp, double beta)
     // short runs the L2 must keep each line for the neighbouring tile.
     if (a.geo.t_dst[0] == 0 && a.geo.t_len[0] >= 6) a.flags |= qk::kStream;
     // Send 16 consecutive tiles (adjacent runs, shared lines and DRAM rows) to one XCD.
-    const uint64_t T = nblocks(h->n);
+    const uint64_t T = nblocks(h);
     for (uint32_t g = 4; g >= 1; --g)
         if (T % (8ull << g) == 0) {
             a.xcd_g = g;
@@ -300,7 +306,7 @@ qaoa_status take_event(qaoa_handle h, hipEvent_t *ev)
 qaoa_status run_pass(qaoa_handle h, int mode, const qk::PassArgs &a)
 {
     if (!h->profiling) {
-        HIPCHECK(h, qk::launch_pass(mode, c64(h), a, nblocks(h->n), h->stream));
+        HIPCHECK(h, qk::launch_pass(mode, c64(h), a, nblocks(h), h->stream));
         return QAOA_OK;
     }
     // reported kinds: 0 forward, 1 turn, 2 backward, 3 / 4 layer-boundary forward / backward
@@ -311,7 +317,7 @@ qaoa_status run_pass(qaoa_handle h, int mode, const qk::PassArgs &a)
     if (st == QAOA_OK) st = take_event(h, &pd.t1);
     if (st != QAOA_OK) return st;
     HIPCHECK(h, hipEventRecord(pd.t0, h->stream));
-    HIPCHECK(h, qk::launch_pass(mode, c64(h), a, nblocks(h->n), h->stream));
+    HIPCHECK(h, qk::launch_pass(mode, c64(h), a, nblocks(h), h->stream));
     HIPCHECK(h, hipEventRecord(pd.t1, h->stream));
     h->pending.push_back(pd);
     return QAOA_OK;
@@ -407,7 +413,7 @@ qaoa_status create_common(int32_t n, int32_t precision, void *stream, qaoa_handl
         return device_fail(nullptr, "hipMemGetInfo", e);
     }
     const double need = (double)h->N * (double)(amp_bytes(precision) + cost_bytes(precision)) +
-                        (double)nblocks(n) * 8.0 * 2 + (1 << 20);
+                        (double)nblocks(n, precision == QAOA_C64) * 8.0 * 2 + (1 << 20);
     if (!fits(h, need, fr)) {
         delete h;
         return fail(QAOA_ERR_OUT_OF_MEMORY, "state and cost diagonal do not fit in free device memory");
@@ -430,7 +436,7 @@ qaoa_status create_common(int32_t n, int32_t precision, void *stream, qaoa_handl
         if (e == hipErrorOutOfMemory) return fail(QAOA_ERR_OUT_OF_MEMORY, "state or cost allocation failed");
         return device_fail(nullptr, "hipMalloc", e);
     }
-    qaoa_status st = ensure_doubles(h, &h->parts, &h->parts_cap, 2 * nblocks(n) + 2);
+    qaoa_status st = ensure_doubles(h, &h->parts, &h->parts_cap, 2 * nblocks(n, precision == QAOA_C64) + 2);
     if (st == QAOA_OK) st = ensure_doubles(h, &h->res, &h->res_cap, 64);
     if (st != QAOA_OK) {
         std::string keep = g_err;
@@ -687,7 +693,7 @@ qaoa_status qaoa_evaluate(qaoa_handle h, int32_t p, const double *gamma, const d
     }
     DeviceGuard dg(h->device);
     h->state_valid = false;
-    const uint64_t T = nblocks(h->n);
+    const uint64_t T = nblocks(h);
     if ((st = ensure_doubles(h, &h->parts, &h->parts_cap, T)) != QAOA_OK) return st;
     if ((st = run_forward(h, p, gamma, beta, false, true)) != QAOA_OK) return st;
     h->state_valid = true;
@@ -717,7 +723,7 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
         if (dev_alloc(h, &h->lam, h->N * amp_bytes(h->prec)) != hipSuccess)
             return fail(QAOA_ERR_OUT_OF_MEMORY, "adjoint vector allocation failed");
     }
-    const uint64_t T = nblocks(h->n);
+    const uint64_t T = nblocks(h);
     const int nslots = 2 * p + 1;
     if ((st = ensure_doubles(h, &h->parts, &h->parts_cap, (size_t)nslots * T)) != QAOA_OK) return st;
     if ((st = ensure_doubles(h, &h->res, &h->res_cap, (size_t)nslots)) != QAOA_OK) return st;

@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kThreads) void k_reset(uint32_t *c) { *c = 0u; }
 template <int WPE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_batch(BatchArgs B)
 {
-    __shared__ double2 lds[kLdsTotal];
+    __shared__ double2 lds[kLdsTotal<double>];
     __shared__ double th[2 * kMaxP], am[2 * kMaxP], av[2 * kMaxP], gr[2 * kMaxP + 1];
     __shared__ int sh_idx;
     const uint32_t tid = threadIdx.x;

@@ -3,19 +3,23 @@
 // Streaming pass kernel (k_pass)
 //   The mixer U_M(b) = prod_j exp(-i b X_j) is a product of commuting
 //   single-qubit rotations (Eq. (1); Sec. IV-B applies them gate by gate).
-//   Instead of one full-state sweep per qubit, a pass loads a tile of 2^12
+//   Instead of one full-state sweep per qubit, a pass loads a tile of 2^TB
 //   amplitudes whose index bits cover a group of qubits, applies every rotation
-//   of that group in registers, and writes the tile back once.  A tile is the
-//   set of indices with bits [0,S) and [h,h+k) free (S + k = 12); the other
-//   n-12 bits are fixed by the workgroup.  Each of the 256 threads holds 16
-//   amplitudes; three register arrangements (A, B, C) each put four different
-//   tile bits into the register index, and two LDS transposes move between
-//   them, so every tile bit is a register bit once.
+//   of that group in registers, and writes the tile back once (TB = 12 for
+//   complex128, 13 for complex64: 64 KiB of state per tile either way).  A
+//   tile is the set of indices with bits [0,S) and [h,h+k) free (S + k = TB);
+//   the other n-TB bits are fixed by the workgroup.  Each thread holds 16
+//   amplitudes (256 threads for complex128, 512 for complex64); three register
+//   arrangements (A, B, C) each put four different tile bits into the register
+//   index, and two LDS transposes move between them, so every tile bit up to
+//   11 is a register bit once.  For TB = 12:
 //     A: lane = bits 0-5,        reg = bits 6-9,         wave = bits 10-11
 //     B: reg = bits 0-3,         lane = bits 4-9,        wave = bits 10-11
 //     C: lane = bits 0-3,6,7,    reg = bits 4,5,10,11,   wave = bits 8-9
-//   Global loads happen in A and stores in C; with S = 2 every access is a
-//   64 B run of consecutive amplitudes, with S >= 6 a 1 KiB run.
+//   For TB = 13 bit 12 is a third wave bit in B and C and lane bit 5 in A,
+//   where its rotation pairs each lane with the lane 32 away.
+//   Global loads happen in A and stores in C; with k = 10 every access is a
+//   64 B run of consecutive amplitudes, with S >= 6 a run of >= 512 B.
 //
 //   The phase layer exp(-i g C) (Sec. IV-B, Euler's formula) is applied to a
 //   tile right after loading it in the first pass of a layer, and the
@@ -40,10 +44,12 @@
 namespace qk {
 namespace {
 
+// Two workgroups per CU (their LDS tiles fill it): 8 waves per CU for
+// complex128, 16 for complex64, whose registers are capped accordingly.
 template <typename R, int MODE, bool TM>
-__global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
+__global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>::MINW))) void k_pass(PassArgs a)
 {
-    __shared__ typename Tr<R>::V lds[kLdsTotal];
+    __shared__ typename Tr<R>::V lds[kLdsTotal<R>];
     const uint64_t b = blockIdx.x;
     // 2^G consecutive tiles per XCD: workgroups are dealt to the 8 XCDs in turn
     const uint32_t G = a.xcd_g;
@@ -62,9 +68,9 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a)
 // Layer-boundary passes (kFwdFuse, kBwdFuse); TM / TM2 are the factored forms
 // of the two rotations.  Same tile order and partial layout as k_pass.
 template <typename R, int MODE, bool TM, bool TM2>
-__global__ __launch_bounds__(kThreads) void k_pass_fuse(PassArgs a)
+__global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>::MINW))) void k_pass_fuse(PassArgs a)
 {
-    __shared__ typename Tr<R>::V lds[kLdsTotal];
+    __shared__ typename Tr<R>::V lds[kLdsTotal<R>];
     const uint64_t b = blockIdx.x;
     const uint32_t G = a.xcd_g;
     const uint64_t t = G ? ((b & ~((8ull << G) - 1ull)) | ((b & 7ull) << G) | ((b >> 3) & ((1ull << G) - 1ull)))
@@ -434,21 +440,23 @@ inline unsigned grid_for(uint64_t N, uint64_t cap = 1ull << 20)
 template <typename R, bool TM>
 static void launch_pass_t(int mode, const PassArgs &a, dim3 grid, hipStream_t s)
 {
-    if (mode == kFwd) hipLaunchKernelGGL((k_pass<R, kFwd, TM>), grid, dim3(kThreads), 0, s, a);
-    else if (mode == kTurn) hipLaunchKernelGGL((k_pass<R, kTurn, TM>), grid, dim3(kThreads), 0, s, a);
+    const dim3 block(Tr<R>::NT);
+    if (mode == kFwd) hipLaunchKernelGGL((k_pass<R, kFwd, TM>), grid, block, 0, s, a);
+    else if (mode == kTurn) hipLaunchKernelGGL((k_pass<R, kTurn, TM>), grid, block, 0, s, a);
     else if (mode == kTurnPhase)
-        hipLaunchKernelGGL((k_pass<R, kTurnPhase, TM>), grid, dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL((k_pass<R, kBwd, TM>), grid, dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL((k_pass<R, kTurnPhase, TM>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_pass<R, kBwd, TM>), grid, block, 0, s, a);
 }
 
 template <typename R, int MODE>
 static void launch_fuse_t(const PassArgs &a, dim3 grid, hipStream_t s)
 {
+    const dim3 block(Tr<R>::NT);
     const int sel = (a.tan_mode ? 2 : 0) + (a.tan_mode2 ? 1 : 0);
-    if (sel == 3) hipLaunchKernelGGL((k_pass_fuse<R, MODE, true, true>), grid, dim3(kThreads), 0, s, a);
-    else if (sel == 2) hipLaunchKernelGGL((k_pass_fuse<R, MODE, true, false>), grid, dim3(kThreads), 0, s, a);
-    else if (sel == 1) hipLaunchKernelGGL((k_pass_fuse<R, MODE, false, true>), grid, dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL((k_pass_fuse<R, MODE, false, false>), grid, dim3(kThreads), 0, s, a);
+    if (sel == 3) hipLaunchKernelGGL((k_pass_fuse<R, MODE, true, true>), grid, block, 0, s, a);
+    else if (sel == 2) hipLaunchKernelGGL((k_pass_fuse<R, MODE, true, false>), grid, block, 0, s, a);
+    else if (sel == 1) hipLaunchKernelGGL((k_pass_fuse<R, MODE, false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_pass_fuse<R, MODE, false, false>), grid, block, 0, s, a);
 }
 
 hipError_t launch_pass(int mode, bool c64, const PassArgs &a, uint64_t nblocks, hipStream_t s)

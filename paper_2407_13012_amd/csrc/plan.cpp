@@ -2,15 +2,16 @@
 //
 // The mixer prod_j exp(-i b X_j) (Eq. (1)) factorises over qubits and its
 // factors commute, so a layer may rotate any group of qubits per sweep over
-// the state.  A sweep here is a tiled pass: a workgroup owns 2^12 amplitudes
-// whose indices differ only in 12 chosen bits (the tile bits) and rotates the
+// the state.  A sweep here is a tiled pass: a workgroup owns 2^TB amplitudes
+// whose indices differ only in TB chosen bits (the tile bits; TB = 12 for
+// 16-byte amplitudes, 13 for 8-byte ones, 64 KiB either way) and rotates the
 // target bits among them.  The plan fixes, for one layer, the tile bits and
 // target bits of each pass:
-//   * pass 0 rotates a contiguous run of low bits [0, 12 - x0) plus x0 high
+//   * pass 0 rotates a contiguous run of low bits [0, TB - x0) plus x0 high
 //     bits, so its global accesses are runs of >= 64 consecutive amplitudes;
-//   * passes 1.. keep the S = 12 - k lowest bits as non-rotated spectators
-//     (runs of 2^S consecutive amplitudes) and rotate k <= 10 further bits
-//     (k <= 9 for 8-byte amplitudes, so that runs stay >= 64 bytes);
+//   * passes 1.. keep the S = TB - k lowest bits as non-rotated spectators
+//     (runs of 2^S consecutive amplitudes) and rotate k <= 10 further bits,
+//     so that runs are >= 64 bytes at either precision;
 //   * bits whose stride spans a 2 MiB page (bit >= 17 for 16-byte amplitudes,
 //     >= 18 for 8-byte ones) are spread evenly over the passes, since every
 //     such target bit doubles the number of pages one tile touches.
@@ -43,26 +44,26 @@ std::vector<std::pair<int, int>> runs_of(uint64_t m, int n)
     return r;
 }
 
-std::vector<PassPlan> plan_simple(int n, int kmax)
+std::vector<PassPlan> plan_simple(int n, int TB, int kmax)
 {
     std::vector<PassPlan> out;
-    out.push_back({low_mask(kTileBits), low_mask(kTileBits)});
-    const int r = n - kTileBits, P = (r + kmax - 1) / kmax;
-    int h = kTileBits;
+    out.push_back({low_mask(TB), low_mask(TB)});
+    const int r = n - TB, P = (r + kmax - 1) / kmax;
+    int h = TB;
     for (int i = 0; i < P; ++i) {
         const int k = r / P + (i < r % P ? 1 : 0);
         const uint64_t tg = low_mask(k) << h;
-        out.push_back({tg | low_mask(kTileBits - k), tg});
+        out.push_back({tg | low_mask(TB - k), tg});
         h += k;
     }
     return out;
 }
 
-bool plan_ok(int n, const std::vector<PassPlan> &pl)
+bool plan_ok(int n, int TB, const std::vector<PassPlan> &pl)
 {
     uint64_t seen = 0;
     for (const PassPlan &p : pl) {
-        if (__builtin_popcountll(p.tile_bits) != std::min(n, kTileBits)) return false;
+        if (__builtin_popcountll(p.tile_bits) != std::min(n, TB)) return false;
         if ((p.target_bits & ~p.tile_bits) || (seen & p.target_bits)) return false;
         seen |= p.target_bits;
         Geometry g;
@@ -75,17 +76,17 @@ bool plan_ok(int n, const std::vector<PassPlan> &pl)
 
 std::vector<PassPlan> plan_passes(int n, bool c64, int kmax)
 {
-    if (n <= kTileBits) return {{low_mask(n), low_mask(n)}};
+    const int TB = tile_bits(c64);
+    if (n <= TB) return {{low_mask(n), low_mask(n)}};
     if (kmax < 1) kmax = 1;
+    // >= TB - 10 spectator bits: runs of >= 4 (16-byte) or >= 8 (8-byte) amplitudes
     if (kmax > 10) kmax = 10;
-    // 8-byte amplitudes: keep >= 3 spectator bits (runs of >= 64 B) in the later passes
-    if (c64 && kmax > 9) kmax = 9;
     const int page = c64 ? 18 : 17;
-    const int r = n - kTileBits, P1 = (r + kmax - 1) / kmax;
+    const int r = n - TB, P1 = (r + kmax - 1) / kmax;
     std::vector<int> k(P1 + 1), x(P1 + 1, 0), cap(P1 + 1);
-    k[0] = kTileBits;
+    k[0] = TB;
     for (int i = 0; i < P1; ++i) k[i + 1] = r / P1 + (i < r % P1 ? 1 : 0);
-    cap[0] = kTileBits - 6;  // pass 0 keeps >= 64 consecutive amplitudes
+    cap[0] = TB - 6;  // pass 0 keeps >= 64 consecutive amplitudes
     for (int i = 1; i <= P1; ++i) cap[i] = k[i];
     int left = std::max(0, n - page);
     while (left > 0) {
@@ -99,8 +100,8 @@ std::vector<PassPlan> plan_passes(int n, bool c64, int kmax)
         if (!moved) break;
     }
     std::vector<PassPlan> out(P1 + 1);
-    int nc = kTileBits - x[0];          // next non-crossing bit to hand out
-    int cr = std::max(page, kTileBits); // next crossing bit to hand out
+    int nc = TB - x[0];           // next non-crossing bit to hand out
+    int cr = std::max(page, TB);  // next crossing bit to hand out
     if (n <= page) cr = n;
     // Crossing bits are handed out in ascending blocks: pass 1 first, then
     // pass 0, then passes 2..  (the order measured fastest at n = 32).
@@ -111,15 +112,15 @@ std::vector<PassPlan> plan_passes(int n, bool c64, int kmax)
     std::vector<uint64_t> crossing(P1 + 1, 0);
     for (int i : order)
         for (int j = 0; j < x[i]; ++j) crossing[i] |= 1ull << cr++;
-    out[0].target_bits = low_mask(kTileBits - x[0]) | crossing[0];
+    out[0].target_bits = low_mask(TB - x[0]) | crossing[0];
     out[0].tile_bits = out[0].target_bits;
     for (int i = 1; i <= P1; ++i) {
         uint64_t tg = crossing[i];
         for (int j = 0; j < k[i] - x[i]; ++j) tg |= 1ull << nc++;
         out[i].target_bits = tg;
-        out[i].tile_bits = tg | low_mask(kTileBits - k[i]);
+        out[i].tile_bits = tg | low_mask(TB - k[i]);
     }
-    if (!plan_ok(n, out)) out = plan_simple(n, kmax);
+    if (!plan_ok(n, TB, out)) out = plan_simple(n, TB, kmax);
     return out;
 }
 

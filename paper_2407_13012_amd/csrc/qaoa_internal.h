@@ -9,10 +9,13 @@
 
 namespace qk {
 
-// Tile geometry of the streaming pass kernel: one workgroup owns 2^12
-// amplitudes, 256 threads x 16 amplitudes in registers.
-constexpr int kTileBits = 12;
-constexpr int kTile = 1 << kTileBits;
+// Tile geometry of the streaming pass kernel: one workgroup of 256 threads
+// owns 2^12 complex128 amplitudes (16 per thread) or 2^13 complex64 ones (32
+// per thread), 64 KiB of state either way.
+constexpr int kTileBits = 12;    // complex128
+constexpr int kTileBits64 = 13;  // complex64
+constexpr int tile_bits(bool c64) { return c64 ? kTileBits64 : kTileBits; }
+constexpr int kTile = 1 << kTileBits;  // elements per workgroup of the plain streaming kernels
 constexpr int kThreads = 256;
 
 // Pass modes.
@@ -20,7 +23,7 @@ enum PassMode : int {
     kFwd = 0,   // one vector: [init|load] [phase] mixer [E] store
     kTurn = 1,  // last forward group fused with the first backward group
     kBwd = 2,   // two vectors: mixer^dag with <lam|X_j|phi>, [phase^dag with <lam|C|phi>]
-    kTurnPhase = 3, // turn pass of a one-pass layer (n <= 12): also applies and undoes the phase
+    kTurnPhase = 3, // turn pass of a one-pass layer (n <= TB): also applies and undoes the phase
     // Layer-boundary passes.  Consecutive layers visit their mixer groups in
     // opposite orders, so the last group of layer l and the first group of
     // layer l+1 share a geometry and one sweep serves both:
@@ -40,9 +43,10 @@ enum PassFlags : int {
     kBetaAcc2 = 128  // kBetaAcc for the second rotation's partials (kBwdFuse)
 };
 
-// One pass of a mixer layer.  A tile is the set of 2^12 basis indices that
-// agree outside `tile_bits`; the pass rotates the qubits in `target_bits`
-// (a subset of tile_bits; the rest are spectators kept for contiguous access).
+// One pass of a mixer layer.  A tile is the set of 2^TB basis indices that
+// agree outside `tile_bits` (TB = tile_bits(c64)); the pass rotates the qubits
+// in `target_bits` (a subset of tile_bits; the rest are spectators kept for
+// contiguous access).
 struct PassPlan {
     uint64_t tile_bits;
     uint64_t target_bits;
@@ -57,14 +61,15 @@ struct Geometry {
     uint32_t t_src[kTileRuns], t_dst[kTileRuns], t_len[kTileRuns];
     uint32_t f_src[kFreeRuns], f_dst[kFreeRuns], f_len[kFreeRuns];
     uint32_t tmask;  // tile-local bits that are rotated
-    uint32_t tbits;  // number of valid tile-local bits (12, or n when n < 12)
+    uint32_t tbits;  // number of valid tile-local bits (TB, or n when n < TB)
 };
 
 // Pass plan of one mixer layer on n qubits (host).  Every qubit is a target of
-// exactly one pass; the first pass holds bits [0, 12 - x) plus x high bits.
+// exactly one pass; the first pass holds bits [0, TB - x) plus x high bits.
 // Qubits whose stride crosses a 2 MiB page are spread evenly over the passes
 // so that no tile touches more than a few dozen pages.
-// kmax bounds the qubits rotated by each pass after the first (at most 10).
+// kmax bounds the qubits rotated by each pass after the first (at most 10, so
+// that at least TB - 10 spectator bits give runs of >= 64 bytes).
 std::vector<PassPlan> plan_passes(int n, bool c64, int kmax = 10);
 // Kernel geometry of a plan entry; returns false if it needs more runs than supported.
 bool make_geometry(int n, const PassPlan &pp, Geometry *g);

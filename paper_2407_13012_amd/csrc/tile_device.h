@@ -6,20 +6,37 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace qk {
 namespace {
 
 template <typename R>
 struct Tr;
+// Amplitude type, cost-entry type and tile shape per precision: 2^TB
+// amplitudes per workgroup of NT = 2^(TB-4) threads (NW = 2^WB waves of 64),
+// NR = 16 amplitudes per thread.
 template <>
 struct Tr<double> {
     using V = double2;
     using CT = double;
+    static constexpr int TB = kTileBits;
+    static constexpr int WB = TB - 10;
+    static constexpr int NW = 1 << WB;
+    static constexpr int NT = 64 * NW;
+    static constexpr int NR = 16;
+    static constexpr int MINW = 1;  // waves per SIMD the pass kernels must allow
 };
 template <>
 struct Tr<float> {
     using V = float2;
     using CT = float;
+    static constexpr int TB = kTileBits64;
+    static constexpr int WB = TB - 10;
+    static constexpr int NW = 1 << WB;
+    static constexpr int NT = 64 * NW;
+    static constexpr int NR = 16;
+    static constexpr int MINW = 4;
 };
 
 // Streaming accesses: with long contiguous runs every line is used once per
@@ -57,24 +74,43 @@ __device__ __forceinline__ void stnt(float2 v, float2 *p)
 
 // ------------------------------------------------------------ tile geometry
 
-// LDS slot of tile element e: one padding slot after every 16 elements.  In all
-// three arrangements any 16 consecutive lanes then hit distinct 16 B bank
-// groups, and the slot is additive over the thread part and the register part
-// of e, so every access is one base register plus an immediate offset.
-constexpr int kLdsSlots = kTile + kTile / 16;
+// LDS slot of tile element e: one padding slot after every 16 elements, and 8
+// more before the upper half of a 13-bit tile.  In all three arrangements any
+// 16 consecutive lanes then hit distinct banks, and the slot is additive over
+// the thread part and the register part of e, so every access is one base
+// register plus an immediate offset.
+template <typename R>
+constexpr int kLdsSlots = (1 << Tr<R>::TB) + (1 << Tr<R>::TB) / 16 + 8 * ((1 << Tr<R>::TB) >> 13);
 // The workgroup's LDS: the padded transpose slots plus room for the per-wave
-// partial sums of the block reduction (4 values x 4 waves of doubles).
-constexpr int kLdsTotal = kLdsSlots + 16;
-__host__ __device__ __forceinline__ constexpr uint32_t lds_slot(uint32_t e) { return e + (e >> 4); }
+// partial sums of the block reduction (4 values x NW waves of doubles).
+template <typename R>
+constexpr int kLdsTotal = kLdsSlots<R> + (int)(4 * Tr<R>::NW * sizeof(double) / sizeof(typename Tr<R>::V));
+template <int WB>
+__host__ __device__ __forceinline__ constexpr uint32_t lds_slot(uint32_t e)
+{
+    return e + (e >> 4) + (WB == 3 ? ((e >> 12) << 3) : 0u);
+}
 
-template <int ARR>
+// Register arrangements of a tile of 2^(10+WB) elements (lane: 6 bits,
+// register index: 4 bits, wave: WB = 2 or 3 bits).  With WB = 2:
+//   A: lane = bits 0-5,      reg = bits 6-9,         wave = bits 10-11
+//   B: reg = bits 0-3,       lane = bits 4-9,        wave = bits 10-11
+//   C: lane = bits 0-3,6,7,  reg = bits 4,5,10,11,   wave = bits 8-9
+// With WB = 3 the extra tile bit 12 is the top wave bit in A and C, and lane
+// bit 1 in B (where the lanes hold bits 4, 12, 5-8 and the waves bits 9-11):
+// it is never a register bit, and its rotation pairs lanes l and l ^ 2 in B,
+// which a DPP quad permutation reaches without LDS traffic.
+template <int ARR, int WB>
 __host__ __device__ __forceinline__ constexpr uint32_t elem(uint32_t lane, uint32_t wave,
                                                             uint32_t r)
 {
     return ARR == 0   ? (lane | (r << 6) | (wave << 10))
-           : ARR == 1 ? (r | (lane << 4) | (wave << 10))
-                      : ((lane & 15u) | ((r & 3u) << 4) | ((lane >> 4) << 6) | (wave << 8) |
-                         ((r >> 2) << 10));
+           : ARR == 1 ? (WB == 2 ? (r | (lane << 4) | (wave << 10))
+                                 : (r | ((lane & 1u) << 4) | (((lane >> 1) & 1u) << 12) | ((lane >> 2) << 5) |
+                                    (wave << 9)))
+           : WB == 2 ? ((lane & 15u) | ((r & 3u) << 4) | ((lane >> 4) << 6) | (wave << 8) | ((r >> 2) << 10))
+                     : ((lane & 15u) | ((r & 3u) << 4) | ((lane >> 4) << 6) | ((wave & 3u) << 8) |
+                        ((r >> 2) << 10) | ((wave >> 2) << 12));
 }
 
 // Tile bit held by register-index bit q in arrangement ARR.
@@ -82,6 +118,14 @@ template <int ARR>
 __host__ __device__ constexpr uint32_t regbit(int q)
 {
     return ARR == 0 ? 6 + q : (ARR == 1 ? q : (q < 2 ? 4 + q : 8 + q));
+}
+
+// Tile bits rotated while the tile is in arrangement ARR (each tile bit once):
+// the register bits, plus in B the lane-held bit 12 of 13-bit tiles.
+template <int ARR, int WB>
+__host__ __device__ constexpr uint32_t owned()
+{
+    return ARR == 0 ? (15u << 6) : ARR == 1 ? (15u | (WB == 3 ? 1u << 12 : 0u)) : ((3u << 4) | (3u << 10));
 }
 
 // Tile-local index -> offset of the amplitude from the tile base.
@@ -142,6 +186,21 @@ __device__ __forceinline__ double imcx_acc(V u, V v, double acc)
 {
     return fma(-(double)u.y, (double)v.x, fma((double)u.x, (double)v.y, acc));
 }
+// complex64: the products of one target bit's 16 register pairs (or 16 lane
+// pairs) are summed in fp32, as accurate as the amplitudes themselves, and
+// each such partial sum is then accumulated in fp64.
+__device__ __forceinline__ float imcx_acc(float2 u, float2 v, float acc)
+{
+    return fmaf(-u.y, v.x, fmaf(u.x, v.y, acc));
+}
+template <typename V>
+struct PairSum {
+    using T = double;
+};
+template <>
+struct PairSum<float2> {
+    using T = float;
+};
 
 // sin and cos of x in fp64.  Cody-Waite reduction x = k pi/2 + r with pi/2
 // split into two 33-bit parts and a remainder (k pi/2 is exact for |k| < 2^20),
@@ -220,9 +279,45 @@ __device__ __forceinline__ void bfly(V &a, V &b, R m)
     }
 }
 
+// Wave bits of a tile of amplitudes of type V (2 for complex128, 3 for complex64).
+template <typename V>
+constexpr int kWaveBits = 2;
+template <>
+constexpr int kWaveBits<float2> = 3;
+
+// Amplitude held by lane l ^ 2 (the partner across tile bit 12 in arrangement
+// B of a 13-bit tile): a DPP quad permutation [2, 3, 0, 1].
+__device__ __forceinline__ float lane_xor2(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, true));
+}
+template <typename V>
+__device__ __forceinline__ V lane_partner(V v)
+{
+    V o;
+    o.x = lane_xor2(v.x);
+    o.y = lane_xor2(v.y);
+    return o;
+}
+
+// The factored rotation of bfly() across lanes: both members of a pair get the
+// same formula, with the partner's amplitude p in place of the other register.
+template <bool TM, typename V, typename R>
+__device__ __forceinline__ void bfly_lane(V &s, V p, R m)
+{
+    if constexpr (TM) {
+        s.x = fma(m, p.y, s.x);
+        s.y = fma(-m, p.x, s.y);
+    } else {
+        s.x = fma(m, s.x, p.y);
+        s.y = fma(m, s.y, -p.x);
+    }
+}
+
 template <int ARR, bool TM, typename V, typename R>
 __device__ __forceinline__ void mix_stage(V (&v)[16], R m, uint32_t tmask)
 {
+    constexpr int WB = kWaveBits<V>;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if ((tmask >> regbit<ARR>(q)) & 1u) {
@@ -231,26 +326,35 @@ __device__ __forceinline__ void mix_stage(V (&v)[16], R m, uint32_t tmask)
                 if (!(r & (1 << q))) bfly<TM>(v[r], v[r | (1 << q)], m);
         }
     }
+    if constexpr (ARR == 1 && WB == 3) {
+        if ((tmask >> 12) & 1u) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) bfly_lane<TM>(v[r], lane_partner(v[r]), m);
+        }
+    }
 }
 
 // Adjoint stage: for each target bit, add Im<lam|X_j|phi> over the register
 // pairs (weighted by sig2, the squared factor both vectors still miss), then
-// apply the factored inverse rotation to both.
+// apply the factored inverse rotation to both.  Across lanes (tile bit 12 of
+// 13-bit tiles, arrangement B) each lane adds Im(conj(lam) phi_partner); the
+// two lanes of a pair together give the pair's term.
 template <int ARR, bool TM, typename V, typename R>
 __device__ __forceinline__ void adj_stage(V (&f)[16], V (&l)[16], R m, uint32_t tmask,
                                           double &sig2, double f2, double &accB)
 {
+    constexpr int WB = kWaveBits<V>;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if ((tmask >> regbit<ARR>(q)) & 1u) {
-            double ps = 0.0;
+            typename PairSum<V>::T ps = 0;
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 if (!(r & (1 << q))) {
                     const int r1 = r | (1 << q);
                     ps = imcx_acc(l[r1], f[r], imcx_acc(l[r], f[r1], ps));
                 }
-            accB = fma(sig2, ps, accB);
+            accB = fma(sig2, (double)ps, accB);
             sig2 *= f2;
 #pragma unroll
             for (int r = 0; r < 16; ++r)
@@ -260,24 +364,53 @@ __device__ __forceinline__ void adj_stage(V (&f)[16], V (&l)[16], R m, uint32_t 
                 }
         }
     }
+    if constexpr (ARR == 1 && WB == 3) {
+        if ((tmask >> 12) & 1u) {
+            typename PairSum<V>::T ps = 0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const V fp = lane_partner(f[r]), lp = lane_partner(l[r]);
+                ps = imcx_acc(l[r], fp, ps);
+                bfly_lane<TM>(l[r], lp, m);
+                bfly_lane<TM>(f[r], fp, m);
+            }
+            accB = fma(sig2, (double)ps, accB);
+            sig2 *= f2;
+        }
+    }
 }
 
 // Sum over the target bits owned by arrangement ARR of Im<lam|X_j|phi> on the
-// register pairs, times w (the product of the factors both vectors miss).
+// register (and lane) pairs, times w (the product of the factors both vectors miss).
 template <int ARR, typename V>
 __device__ __forceinline__ void beta_terms(const V (&f)[16], const V (&l)[16], uint32_t tmask,
                                            double w, double &accB)
 {
+    constexpr int WB = kWaveBits<V>;
+    using PS = typename PairSum<V>::T;
+    // complex128: one fp64 chain over all bits; complex64: fp32 per bit
     double ps = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if ((tmask >> regbit<ARR>(q)) & 1u) {
+            PS pq = 0;
+            if constexpr (std::is_same<PS, double>::value) pq = ps;
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 if (!(r & (1 << q))) {
                     const int r1 = r | (1 << q);
-                    ps = imcx_acc(l[r1], f[r], imcx_acc(l[r], f[r1], ps));
+                    pq = imcx_acc(l[r1], f[r], imcx_acc(l[r], f[r1], pq));
                 }
+            if constexpr (std::is_same<PS, double>::value) ps = pq;
+            else ps += (double)pq;
+        }
+    }
+    if constexpr (ARR == 1 && WB == 3) {
+        if ((tmask >> 12) & 1u) {
+            PS pq = 0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) pq = imcx_acc(l[r], lane_partner(f[r]), pq);
+            ps += (double)pq;
         }
     }
     accB = fma(w, ps, accB);
@@ -305,13 +438,14 @@ __device__ __forceinline__ void lds_barrier()
 template <int FROM, int TO, typename V>
 __device__ __forceinline__ void xpose(V (&v)[16], V *lds, uint32_t lane, uint32_t wave)
 {
-    V *wr = lds + lds_slot(elem<FROM>(lane, wave, 0));
-    V *rd = lds + lds_slot(elem<TO>(lane, wave, 0));
+    constexpr int WB = kWaveBits<V>;
+    V *wr = lds + lds_slot<WB>(elem<FROM, WB>(lane, wave, 0));
+    V *rd = lds + lds_slot<WB>(elem<TO, WB>(lane, wave, 0));
 #pragma unroll
-    for (int r = 0; r < 16; ++r) wr[lds_slot(elem<FROM>(0, 0, r))] = v[r];
+    for (int r = 0; r < 16; ++r) wr[lds_slot<WB>(elem<FROM, WB>(0, 0, r))] = v[r];
     lds_barrier();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = rd[lds_slot(elem<TO>(0, 0, r))];
+    for (int r = 0; r < 16; ++r) v[r] = rd[lds_slot<WB>(elem<TO, WB>(0, 0, r))];
     lds_barrier();
 }
 
@@ -336,10 +470,12 @@ __device__ __forceinline__ double block_sum(double x, double *scratch)
     return r;
 }
 
-// Fixed-order sums over the 256-thread block of up to four values (each as
-// block_sum would give it), valid in thread 0, with one barrier.  `red` holds
-// 16 doubles outside the transpose slots, so the caller's next LDS writes need
-// no further barrier: thread 0 reads `red` before it reaches the next one.
+// Fixed-order sums over a block of NW waves of up to four values (with NW = 4
+// each as block_sum would give it), valid in thread 0, with one barrier.
+// `red` holds 4 NW doubles outside the transpose slots, so the caller's next
+// LDS writes need no further barrier: thread 0 reads `red` before it reaches
+// the next one.
+template <int NW>
 __device__ __forceinline__ void block_sums4(const double (&x)[4], const bool (&want)[4], double *red,
                                             double (&out)[4])
 {
@@ -349,14 +485,18 @@ __device__ __forceinline__ void block_sums4(const double (&x)[4], const bool (&w
     for (int k = 0; k < 4; ++k) w[k] = want[k] ? wave_sum(x[k]) : 0.0;
     if (lane == 0) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) red[4 * k + wave] = w[k];
+        for (int k = 0; k < 4; ++k) red[NW * k + wave] = w[k];
     }
     lds_barrier();
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         out[k] = 0.0;
-        if (threadIdx.x == 0 && want[k])
-            out[k] = ((red[4 * k] + red[4 * k + 1]) + red[4 * k + 2]) + red[4 * k + 3];
+        if (threadIdx.x == 0 && want[k]) {
+            double t = red[NW * k];
+#pragma unroll
+            for (int i = 1; i < NW; ++i) t += red[NW * k + i];
+            out[k] = t;
+        }
     }
 }
 
@@ -383,16 +523,17 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
 {
     using V = typename Tr<R>::V;
     using CT = typename Tr<R>::CT;
+    constexpr int WB = Tr<R>::WB, NR = Tr<R>::NR;
     // The thread index is passed through an empty asm so that the per-thread
     // addresses and masks derived from it are formed inside each tile pass: a
     // caller that loops over tiles would otherwise keep them live across the
-    // loop, next to the 16 amplitudes per thread.
+    // loop, next to the amplitudes held per thread.
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const uint32_t lane = tid & 63u, wave = tid >> 6;
     const Geometry &g = a.geo;
     const uint64_t base = tile_base(t, g);
-    const bool full = g.tbits == (uint32_t)kTileBits;
+    const bool full = g.tbits == (uint32_t)Tr<R>::TB;
     const uint32_t lim = 1u << g.tbits;
     const uint32_t tmask = g.tmask;
     const bool strm = (a.flags & kStream) != 0;
@@ -402,12 +543,12 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
 
     // Global index of register r in arrangement A / C: a per-thread part plus a
     // part that depends on r only (the same for every thread of the grid).
-    const uint64_t thrA = base | dep(elem<0>(lane, wave, 0), g);
-    const uint64_t thrC = base | dep(elem<2>(lane, wave, 0), g);
-#define ZA(r) (thrA | dep(elem<0>(0, 0, (r)), g))
-#define ZC(r) (thrC | dep(elem<2>(0, 0, (r)), g))
-#define VA(r) (full || elem<0>(lane, wave, (r)) < lim)
-#define VC(r) (full || elem<2>(lane, wave, (r)) < lim)
+    const uint64_t thrA = base | dep(elem<0, WB>(lane, wave, 0), g);
+    const uint64_t thrC = base | dep(elem<2, WB>(lane, wave, 0), g);
+#define ZA(r) (thrA | dep(elem<0, WB>(0, 0, (r)), g))
+#define ZC(r) (thrC | dep(elem<2, WB>(0, 0, (r)), g))
+#define VA(r) (full || elem<0, WB>(lane, wave, (r)) < lim)
+#define VC(r) (full || elem<2, WB>(lane, wave, (r)) < lim)
     // Block sums of the tile's E, <lam|X|phi> and <lam|C|phi> terms, taken
     // before the final stores so that the workgroup retires right after issuing them.
 #define REDUCE()                                                                        \
@@ -415,7 +556,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
         if (wantE || wantB || wantG) {                                                  \
             const double x_[4] = {accE, accB, accG, accB2};                             \
             const bool w_[4] = {wantE, wantB, wantG, MODE == kBwdFuse};                 \
-            block_sums4(x_, w_, (double *)(lds + kLdsSlots), sums);                     \
+            block_sums4<Tr<R>::NW>(x_, w_, (double *)(lds + kLdsSlots<R>), sums);                \
         } else {                                                                        \
             sums[0] = sums[1] = sums[2] = sums[3] = 0.0;                                \
         }                                                                               \
@@ -435,29 +576,33 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
     const bool wantG = phaseOut;
     double accB2 = 0.0;  // kBwdFuse: <lam|X|phi> terms of the second rotation's layer
     const bool costC = TURN || phaseOut || (MODE == kFwd && (a.flags & kEOut));
-    CT cin[16], cv[16];
+    // Two-vector passes of complex64 tiles (16 waves per CU, 128 registers)
+    // load the cost entries where they are used, which keeps them out of the
+    // register budget of the rotations; the other waves cover the latency.
+    constexpr bool kLateCost = Tr<R>::NW == 8 && (MODE == kBwd || MODE == kBwdFuse);
+    CT cin[NR], cv[NR];
     if (phaseIn) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) cin[r] = VA(r) ? ld(&cost[ZA(r)], strm) : (CT)0;
+        for (int r = 0; r < NR; ++r) cin[r] = VA(r) ? ld(&cost[ZA(r)], strm) : (CT)0;
     }
-    if (costC) {
+    if (costC && !kLateCost) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) cv[r] = VC(r) ? ld(&cost[ZC(r)], strm) : (CT)0;
+        for (int r = 0; r < NR; ++r) cv[r] = VC(r) ? ld(&cost[ZC(r)], strm) : (CT)0;
     }
 
     if constexpr (MODE == kFwd || TURN) {
-        V v[16];
+        V v[NR];
         if (a.flags & kInit) {
             const V a0 = {(R)a.amp0, (R)0};
 #pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = VA(r) ? a0 : zero;
+            for (int r = 0; r < NR; ++r) v[r] = VA(r) ? a0 : zero;
         } else {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = VA(r) ? ld(&psi[ZA(r)], strm) : zero;
+            for (int r = 0; r < NR; ++r) v[r] = VA(r) ? ld(&psi[ZA(r)], strm) : zero;
         }
         if (phaseIn) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
+            for (int r = 0; r < NR; ++r)
                 if (VA(r)) {
                     R c, s;
                     phase_cs(-a.gamma_in, cin[r], c, s);
@@ -472,26 +617,26 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
         mix_stage<2, TM>(v, mf, tmask);
         const R sf = (R)a.scl_f;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = vscale(v[r], sf);
+        for (int r = 0; r < NR; ++r) v[r] = vscale(v[r], sf);
 
         if constexpr (MODE == kFwd) {
             if (a.flags & kEOut) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) accE += (double)cv[r] * norm2(v[r]);
+                for (int r = 0; r < NR; ++r) accE += (double)cv[r] * norm2(v[r]);
             }
             REDUCE();
             if (!(a.flags & kNoStore)) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
+                for (int r = 0; r < NR; ++r)
                     if (VC(r)) st(v[r], &psi[ZC(r)], strm);
             }
         } else {
             // v is the final state phi on this tile: E, lam = C phi, then undo the
             // group on both, visiting the register arrangements C, B, A; lam is
             // stored from A (from C when the phase is undone too).
-            V l[16];
+            V l[NR];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            for (int r = 0; r < NR; ++r) {
                 accE += (double)cv[r] * norm2(v[r]);
                 l[r] = vscale(v[r], (R)cv[r]);
             }
@@ -505,15 +650,15 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                 // both vectors sit at the same point.  Arrangement C: the final point.
                 // Then undo C's rotations on lam only; phi before stage C is still in
                 // LDS from the forward B->C transpose, so it is re-read, not recomputed.
-                const int kA = popc(tmask & (15u << 6)), kB = popc(tmask & 15u);
-                const int kC = popc(tmask & ((3u << 4) | (3u << 10)));
+                const int kA = popc(tmask & owned<0, WB>()), kB = popc(tmask & owned<1, WB>());
+                const int kC = popc(tmask & owned<2, WB>());
                 const double ff = a.fac_f, fb = a.fac_b;
                 beta_terms<2>(v, l, tmask, 1.0, accB);
                 mix_stage<2, TM>(l, mb, tmask);
                 {
-                    const V *rd = lds + lds_slot(elem<1>(lane, wave, 0));
+                    const V *rd = lds + lds_slot<WB>(elem<1, WB>(lane, wave, 0));
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) v[r] = rd[lds_slot(elem<1>(0, 0, r))];
+                    for (int r = 0; r < NR; ++r) v[r] = rd[lds_slot<WB>(elem<1, WB>(0, 0, r))];
                     lds_barrier();
                 }
                 xpose<2, 1>(l, lds, lane, wave);
@@ -528,7 +673,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                 REDUCE();
                 if (!(a.flags & kNoStore)) {
 #pragma unroll
-                    for (int r = 0; r < 16; ++r)
+                    for (int r = 0; r < NR; ++r)
                         if (VA(r)) st(vscale(l[r], sb), &lam[ZA(r)], strm);
                 }
             } else {
@@ -544,7 +689,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                 xpose<0, 2>(l, lds, lane, wave);
                 xpose<0, 2>(v, lds, lane, wave);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
+                for (int r = 0; r < NR; ++r) {
                     l[r] = vscale(l[r], sb);
                     if (VC(r)) {
                         accG += (double)cv[r] * imcx(l[r], vscale(v[r], sb));
@@ -556,15 +701,15 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                 REDUCE();
                 if (!(a.flags & kNoStore)) {
 #pragma unroll
-                    for (int r = 0; r < 16; ++r)
+                    for (int r = 0; r < NR; ++r)
                         if (VC(r)) st(l[r], &lam[ZC(r)], strm);
                 }
             }
         }
     } else {
-        V f[16], l[16];
+        V f[NR], l[NR];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < NR; ++r) {
             const bool ok = VA(r);
             f[r] = ok ? ld(&psi[ZA(r)], strm) : zero;
             l[r] = ok ? ld(&lam[ZA(r)], strm) : zero;
@@ -581,13 +726,17 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
         adj_stage<2, TM>(f, l, mb, tmask, sig2, f2, accB);
         const R sb = (R)a.scl_b;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < NR; ++r) {
             f[r] = vscale(f[r], sb);
             l[r] = vscale(l[r], sb);
         }
         if (phaseOut) {
+            if constexpr (kLateCost) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
+                for (int r = 0; r < NR; ++r) cv[r] = VC(r) ? ld(&cost[ZC(r)], strm) : (CT)0;
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
                 if (VC(r)) {
                     accG += (double)cv[r] * imcx(l[r], f[r]);
                     R c, s;
@@ -611,7 +760,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
             REDUCE();
             const R sb2 = (R)a.scl_b2;
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
+            for (int r = 0; r < NR; ++r)
                 if (VA(r)) {
                     st(vscale(f[r], sb2), &psi[ZA(r)], strm);
                     st(vscale(l[r], sb2), &lam[ZA(r)], strm);
@@ -620,7 +769,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
             REDUCE();
             if (!(a.flags & kNoStore)) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
+                for (int r = 0; r < NR; ++r)
                     if (VC(r)) {
                         st(f[r], &psi[ZC(r)], strm);
                         st(l[r], &lam[ZC(r)], strm);
@@ -643,28 +792,29 @@ __device__ __forceinline__ void tile_pass_fwd_fuse(const PassArgs &a, uint64_t t
 {
     using V = typename Tr<R>::V;
     using CT = typename Tr<R>::CT;
+    constexpr int WB = Tr<R>::WB, NR = Tr<R>::NR;
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const uint32_t lane = tid & 63u, wave = tid >> 6;
     const Geometry &g = a.geo;
     const uint64_t base = tile_base(t, g);
-    const bool full = g.tbits == (uint32_t)kTileBits;
+    const bool full = g.tbits == (uint32_t)Tr<R>::TB;
     const uint32_t lim = 1u << g.tbits;
     const uint32_t tmask = g.tmask;
     const bool strm = (a.flags & kStream) != 0;
     V *psi = (V *)a.psi;
     const CT *cost = (const CT *)a.cost;
-    const uint64_t thrA = base | dep(elem<0>(lane, wave, 0), g);
-    const uint64_t thrC = base | dep(elem<2>(lane, wave, 0), g);
+    const uint64_t thrA = base | dep(elem<0, WB>(lane, wave, 0), g);
+    const uint64_t thrC = base | dep(elem<2, WB>(lane, wave, 0), g);
     const V zero = {(R)0, (R)0};
-    CT cv[16];
-    V v[16];
+    CT cv[NR];
+    V v[NR];
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-        cv[r] = (full || elem<2>(lane, wave, r) < lim) ? ld(&cost[thrC | dep(elem<2>(0, 0, r), g)], strm) : (CT)0;
+    for (int r = 0; r < NR; ++r)
+        cv[r] = (full || elem<2, WB>(lane, wave, r) < lim) ? ld(&cost[thrC | dep(elem<2, WB>(0, 0, r), g)], strm) : (CT)0;
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-        v[r] = (full || elem<0>(lane, wave, r) < lim) ? ld(&psi[thrA | dep(elem<0>(0, 0, r), g)], strm) : zero;
+    for (int r = 0; r < NR; ++r)
+        v[r] = (full || elem<0, WB>(lane, wave, r) < lim) ? ld(&psi[thrA | dep(elem<0, WB>(0, 0, r), g)], strm) : zero;
     const R m1 = (R)a.mul_f, m2 = (R)a.mul_f2;
     mix_stage<0, TM>(v, m1, tmask);
     xpose<0, 1>(v, lds, lane, wave);
@@ -673,7 +823,7 @@ __device__ __forceinline__ void tile_pass_fwd_fuse(const PassArgs &a, uint64_t t
     mix_stage<2, TM>(v, m1, tmask);
     const R s1 = (R)a.scl_f;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < NR; ++r) {
         R c, s;
         phase_cs(-a.gamma_in, cv[r], c, s);
         v[r] = cmul(vscale(v[r], s1), c, s);
@@ -687,8 +837,8 @@ __device__ __forceinline__ void tile_pass_fwd_fuse(const PassArgs &a, uint64_t t
     uint64_t thrS = thrA;  // see tile_pass_bwd_fuse
     asm volatile("" : "+v"(thrS));
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-        if (full || elem<0>(lane, wave, r) < lim) st(vscale(v[r], s2), &psi[thrS | dep(elem<0>(0, 0, r), g)], strm);
+    for (int r = 0; r < NR; ++r)
+        if (full || elem<0, WB>(lane, wave, r) < lim) st(vscale(v[r], s2), &psi[thrS | dep(elem<0, WB>(0, 0, r), g)], strm);
 }
 
 }  // namespace

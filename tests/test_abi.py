@@ -143,11 +143,12 @@ def test_python_binding_has_c_names():
 def test_pass_plan_invariants(prec):
     from paper_2407_13012_amd import qaoa_pass_plan
     page = 17 if prec == "c128" else 18
+    tb = 12 if prec == "c128" else 13  # 64 KiB tiles: 2^12 x 16 B or 2^13 x 8 B
     for n in range(1, 41):
         plan = qaoa_pass_plan(n, prec)
         seen = 0
         for i, (tile, tgt) in enumerate(plan):
-            assert bin(tile).count("1") == min(n, 12)
+            assert bin(tile).count("1") == min(n, tb)
             assert tgt & ~tile == 0 and tgt & seen == 0
             assert tile < (1 << n)
             seen |= tgt
@@ -157,13 +158,13 @@ def test_pass_plan_invariants(prec):
             # the first pass starts with >= 6 consecutive low target bits (>= 64 amplitudes)
             if i == 0:
                 assert tgt & 63 == min(63, (1 << n) - 1)
-            elif n > 12:
+            elif n > tb:
                 # at least 2 spectator bits (>= 4 consecutive amplitudes, 64 B at complex128),
                 # at least 3 at complex64 (again >= 64 B)
                 assert spect >= (3 if prec == "c128" else 7)
         assert seen == (1 << n) - 1
-        kmax = 10 if prec == "c128" else 9  # 8-byte amplitudes keep >= 3 spectator bits
-        assert len(plan) == (1 if n <= 12 else 1 + -(-(n - 12) // kmax))
+        # at most 10 targets per later pass at either precision
+        assert len(plan) == (1 if n <= tb else 1 + -(-(n - tb) // 10))
         # page-crossing qubits are spread evenly
         X = max(0, n - page)
         if X:
@@ -177,6 +178,18 @@ def test_pass_plan_n32_geometry():
     assert len(plan) == 3
     assert [bin(t >> 17).count("1") for _, t in plan] == [5, 5, 5]
     assert plan[0][1] & 127 == 127          # 7 consecutive low qubits in the first pass
+
+
+def test_pass_plan_n32_complex64_geometry():
+    # 2^13-amplitude tiles: three sweeps per layer, as at complex128, with runs
+    # of >= 8 amplitudes (64 B) in the later sweeps
+    from paper_2407_13012_amd import qaoa_pass_plan
+    plan = qaoa_pass_plan(32, "c64")
+    assert len(plan) == 3
+    assert [bin(t).count("1") for t, _ in plan] == [13, 13, 13]
+    assert [bin(g).count("1") for _, g in plan] == [13, 10, 9]
+    assert min(bin(tile & ~tgt).count("1") for tile, tgt in plan[1:]) == 3
+    assert sorted(bin(t >> 18).count("1") for _, t in plan) == [4, 5, 5]
 
 
 def test_pass_plan_rejects():

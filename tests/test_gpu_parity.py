@@ -286,7 +286,10 @@ def test_sample_errors():
 
 # ---------------------------------------------------------------- complex64
 
-@pytest.mark.parametrize("n,p", [(6, 2), (12, 3), (17, 3), (23, 2)])
+# complex64 tiles hold 2^13 amplitudes: n = 12 is a partial tile, 13 one full
+# tile, 14 a 13-qubit pass plus a one-qubit pass, 24 three passes per layer
+# (both layer-boundary sweeps at p = 3)
+@pytest.mark.parametrize("n,p", [(6, 2), (12, 3), (13, 2), (14, 3), (17, 3), (23, 2), (24, 3)])
 def test_complex64_against_fp64_oracle(n, p):
     inst = mk("er", n, 400 + n)
     C = oracle.cost_of(inst)
