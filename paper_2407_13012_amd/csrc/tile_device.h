@@ -735,14 +735,18 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
 #pragma unroll
                 for (int r = 0; r < NR; ++r) cv[r] = VC(r) ? ld(&cost[ZC(r)], strm) : (CT)0;
             }
+            // the last sweep stores nothing, so it skips the phase undo
+            const bool undo = MODE == kBwdFuse || !(a.flags & kNoStore);
 #pragma unroll
             for (int r = 0; r < NR; ++r)
                 if (VC(r)) {
                     accG += (double)cv[r] * imcx(l[r], f[r]);
-                    R c, s;
-                    phase_cs(a.gamma_out, cv[r], c, s);
-                    f[r] = cmul(f[r], c, s);
-                    l[r] = cmul(l[r], c, s);
+                    if (undo) {
+                        R c, s;
+                        phase_cs(a.gamma_out, cv[r], c, s);
+                        f[r] = cmul(f[r], c, s);
+                        l[r] = cmul(l[r], c, s);
+                    }
                 }
         }
         if constexpr (MODE == kBwdFuse) {
