@@ -398,7 +398,10 @@ def main() -> int:
         dt64, prof64 = time_gradients(q64, gamma, beta, args.steps, 1)
         E64, _, _ = q64.gradient(gamma, beta)
         q64.close()
+        mb64 = model_bytes_per_amp(args.n, p, 8, 4)
         extra["c64"] = {"grad_evals_per_s": args.steps / dt64, "ms_per_step": 1e3 * dt64 / args.steps,
+                        "model_bytes_per_amp": mb64,
+                        "model_roofline_frac": mb64 * 2.0 ** args.n / (dt64 / args.steps) / (HBM_PEAK_GBS * 1e9),
                         "E": E64, "E_rel_diff_vs_c128": abs(E64 - E) / max(abs(E), 1.0),
                         "passes": {k: {"launches": v[0], "ms": v[1], "bytes": v[2],
                                        "gbs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
