@@ -9,14 +9,14 @@
 
 namespace qk {
 
-// Tile geometry of the streaming pass kernel: one workgroup of 256 threads
-// owns 2^12 complex128 amplitudes (16 per thread) or 2^13 complex64 ones (32
-// per thread), 64 KiB of state either way.
+// Tile geometry of the streaming pass kernel: a workgroup owns 2^12
+// complex128 amplitudes (256 threads) or 2^13 complex64 ones (512 threads),
+// 16 per thread and 64 KiB of state either way.
 constexpr int kTileBits = 12;    // complex128
 constexpr int kTileBits64 = 13;  // complex64
 constexpr int tile_bits(bool c64) { return c64 ? kTileBits64 : kTileBits; }
 constexpr int kTile = 1 << kTileBits;  // elements per workgroup of the plain streaming kernels
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;          // threads per workgroup of every kernel but the complex64 passes
 
 // Pass modes.
 enum PassMode : int {
