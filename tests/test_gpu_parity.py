@@ -309,6 +309,28 @@ def test_complex64_against_fp64_oracle(n, p):
     assert np.max(np.abs(db - db_ref)) / gscale <= 1e-4
 
 
+# Both factored rotation forms (|cos b| >= |sin b| and the reverse, and
+# negative angles) on complex64 tiles whose bit 12 is rotated across lanes, in
+# every pairing of forms that the layer-boundary sweeps combine (24 qubits:
+# three sweeps per layer).
+@pytest.mark.parametrize("n", [13, 20, 24])
+def test_complex64_rotation_forms(n):
+    inst = mk("qubo", n, 700 + n)
+    C = oracle.cost_of(inst)
+    gamma = np.array([0.35, -0.2, 0.6, 0.15])
+    beta = np.array([0.3, 1.2, -2.0, 0.5])
+    E_ref, dg_ref, db_ref = oracle.gradient(n, C, gamma, beta)
+    psi_ref = oracle.state(n, C, gamma, beta)
+    with H(inst, "c64") as q:
+        psi = q.statevector(gamma, beta)
+        assert np.max(np.abs(psi - psi_ref)) < 1e-5
+        E, dg, db = q.gradient(gamma, beta)
+    gscale = max(np.max(np.abs(np.concatenate([dg_ref, db_ref]))), 1.0)
+    assert abs(E - E_ref) / max(abs(E_ref), 1.0) <= 1e-4
+    assert np.max(np.abs(dg - dg_ref)) / gscale <= 1e-4
+    assert np.max(np.abs(db - db_ref)) / gscale <= 1e-4
+
+
 # ---------------------------------------------------------------- named workloads
 
 def test_workload_small_full_parity():
