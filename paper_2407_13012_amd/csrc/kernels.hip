@@ -45,9 +45,10 @@ namespace qk {
 namespace {
 
 // Two workgroups per CU (their LDS tiles fill it): 8 waves per CU for
-// complex128, 16 for complex64, whose registers are capped accordingly.
+// complex128, 16 for complex64, whose registers are capped accordingly.  The
+// one-pass turn (n <= TB) runs a single workgroup and keeps the full register file.
 template <typename R, int MODE, bool TM>
-__global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>::MINW))) void k_pass(PassArgs a)
+__global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(MODE == kTurnPhase ? 1 : Tr<R>::MINW))) void k_pass(PassArgs a)
 {
     __shared__ typename Tr<R>::V lds[kLdsTotal<R>];
     const uint64_t b = blockIdx.x;
