@@ -447,8 +447,8 @@ def main() -> int:
             "state_bytes": int(N * s), "precision": args.precision,
         },
         "roofline": roofline,
-        # whole E+G against the byte model of the survey (p(6 P s + 2c) + c - 2s per
-        # amplitude with P = ceil(n / kmax)): the roofline figure the target refers to
+        # whole E+G against the pass byte model p(6 P s + 2c) + c - 2s per amplitude
+        # with P = ceil(n / kmax) (kmax 13 for 16-byte amplitudes, 14 for 8-byte ones)
         "step_roofline": {"bound": "hbm", "model_bytes_per_amp": extra["model_bytes_per_amp"],
                           "implemented_bytes_per_amp": extra["implemented_bytes_per_amp"],
                           "achieved": extra["model_bytes_per_amp"] * N / (ms_per_step * 1e-3) / 1e9,

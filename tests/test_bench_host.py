@@ -2,7 +2,7 @@
 import bench
 
 
-def test_survey_byte_model_values():
+def test_pass_byte_model_values():
     # p (6 P s + 2 c) + c - 2 s with P = ceil(n / kmax): 888 B/amp at the headline
     # configuration (n = 32, p = 3, complex128), 1224 at n = 26, p = 6, 444 for complex64
     assert bench.model_bytes_per_amp(32, 3, 16, 8) == 888

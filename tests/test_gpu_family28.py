@@ -3,7 +3,8 @@ stored-state adjoint gradient handles in host memory: 7 x 4 GiB), in the same
 three-sweep-per-layer pass structure as n = 32, against the oracle element by
 element: E within 1e-10 * sum|w|, gradients within 1e-8; complex64 within
 1e-4 relative.  Also a throughput floor at n = 32 (0.70 of the HBM roofline
-under the survey's byte model) as a regression check."""
+under the pass byte model p(6 P s + 2c) + c - 2s per amplitude) as a
+regression check."""
 import time
 
 import numpy as np
