@@ -46,7 +46,8 @@ typedef enum {
 
 typedef enum {
     QAOA_C128 = 0, /* complex128 state, fp64 cost diagonal */
-    QAOA_C64 = 1   /* complex64 state, fp32 cost diagonal; phases reduced in fp64, sums in fp64 */
+    QAOA_C64 = 1   /* complex64 state, fp32 cost diagonal; phases reduced in fp64, sums in fp64
+                      (a thread's 16 pair products for one qubit are summed in fp32 first) */
 } qaoa_precision;
 
 /* Largest supported qubit count (further bounded by free device memory). */
