@@ -609,6 +609,14 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                     v[r] = cmul(v[r], c, s);
                 }
         }
+        // complex128 turn: the loaded tile (the state before the group, in
+        // arrangement A) stays in registers for the terms of A's bits at the end
+        constexpr bool kKeep0 = MODE == kTurn && WB == 2;
+        V v0[kKeep0 ? NR : 1];
+        if constexpr (kKeep0) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) v0[r] = v[r];
+        }
         const R mf = (R)a.mul_f;
         mix_stage<0, TM>(v, mf, tmask);
         xpose<0, 1>(v, lds, lane, wave);
@@ -665,11 +673,19 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                 // lam misses fb^kC, phi (forward stages A, B) misses ff^(kA+kB)
                 beta_terms<1>(v, l, tmask, upow(fb, kC) * upow(ff, kA + kB), accB);
                 mix_stage<1, TM>(l, mb, tmask);
-                mix_stage<1, TM>(v, mb, tmask);
-                xpose<1, 0>(v, lds, lane, wave);
-                xpose<1, 0>(l, lds, lane, wave);
-                beta_terms<0>(v, l, tmask, upow(fb, kC + 2 * kB) * upow(ff, kA + kB), accB);
-                mix_stage<0, TM>(l, mb, tmask);
+                if constexpr (kKeep0) {
+                    // A's bits at the point before the group: the loaded phi (exact)
+                    // and lam with the whole group undone (missing fb^k)
+                    xpose<1, 0>(l, lds, lane, wave);
+                    mix_stage<0, TM>(l, mb, tmask);
+                    beta_terms<0>(v0, l, tmask, upow(fb, kA + kB + kC), accB);
+                } else {
+                    mix_stage<1, TM>(v, mb, tmask);
+                    xpose<1, 0>(v, lds, lane, wave);
+                    xpose<1, 0>(l, lds, lane, wave);
+                    beta_terms<0>(v, l, tmask, upow(fb, kC + 2 * kB) * upow(ff, kA + kB), accB);
+                    mix_stage<0, TM>(l, mb, tmask);
+                }
                 REDUCE();
                 if (!(a.flags & kNoStore)) {
 #pragma unroll
