@@ -265,6 +265,29 @@ def test_sampling_chi_square_large():
     assert scipy.stats.chi2.sf(stat, keep.sum() - 1) > 1e-3
 
 
+def test_sampling_complex64_chi_square():
+    # complex64 probabilities differ from the fp64 oracle's by ~1e-7 relative, so
+    # shots are compared in distribution; objective values are the fp32 diagonal
+    import scipy.stats
+    n = 18
+    inst = mk("er", n, 77)
+    C = oracle.cost_of(inst)
+    gamma, beta = qi.ramp_with_noise(2, seed=[77, 1])
+    psi = oracle.state(n, C, gamma, beta)
+    with H(inst, "c64") as q:
+        q.statevector(gamma, beta, copy=False)
+        z, c = q.sample(200000, 99)
+    zi = z.astype(np.int64)
+    assert np.array_equal(c, C[zi].astype(np.float32).astype(np.float64))
+    bins = zi >> (n - 8)
+    probs = np.bincount(np.arange(1 << n) >> (n - 8), weights=np.abs(psi) ** 2, minlength=256)
+    obs = np.bincount(bins, minlength=256)
+    exp = probs * z.size
+    keep = exp >= 5
+    stat = ((obs[keep] - exp[keep]) ** 2 / exp[keep]).sum()
+    assert scipy.stats.chi2.sf(stat, keep.sum() - 1) > 1e-3
+
+
 def test_sample_errors():
     from paper_2407_13012_amd import QaoaError
     inst = mk("er", 10, 1)
