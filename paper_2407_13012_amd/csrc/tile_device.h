@@ -244,7 +244,12 @@ __device__ __forceinline__ void sincos_cw(double x, double &s, double &c)
 }
 
 // cos / sin of g * C.  complex128: fp64.  complex64: the product is formed and
-// reduced modulo 2 pi in fp64, then an fp32 sincos is taken.
+// reduced to x = k pi/2 + r, |r| <= pi/4, in fp64 (pi/2 as the double nearest
+// it plus the remainder), then the Taylor series of sin to r^9 and of cos to
+// r^8 are summed in fp32 (truncation below 3e-8, under half an fp32 ulp of
+// cos r >= 0.7).  r is clamped to [-pi/4, pi/4], so even arguments too large
+// for the reduction (|x| beyond ~2^50, far past fp32 phase resolution) give a
+// unit-modulus factor.
 __device__ __forceinline__ void phase_cs(double g, double cval, double &c, double &s)
 {
     sincos_cw(g * cval, s, c);
@@ -252,10 +257,25 @@ __device__ __forceinline__ void phase_cs(double g, double cval, double &c, doubl
 __device__ __forceinline__ void phase_cs(double g, float cval, float &c, float &s)
 {
     const double th = g * (double)cval;
-    const double k = rint(th * 0.15915494309189535);
-    double r = fma(-k, 6.283185307179586, th);
-    r = fma(-k, 2.4492935982947064e-16, r);
-    sincosf((float)r, &s, &c);
+    const double k = rint(th * 0.6366197723675814);  // 2/pi
+    double rd = fma(-k, 1.5707963267948966, th);
+    rd = fma(-k, 6.123233995736766e-17, rd);
+    const float r = fminf(fmaxf((float)rd, -0.785398163f), 0.785398163f), r2 = r * r;
+    float ps = 2.7557319e-6f;               //  1/9!
+    ps = fmaf(ps, r2, -1.98412698e-4f);     // -1/7!
+    ps = fmaf(ps, r2, 8.33333333e-3f);      //  1/5!
+    ps = fmaf(ps, r2, -0.166666667f);       // -1/3!
+    const float sr = fmaf(ps * r2, r, r);
+    float pc = 2.48015873e-5f;              //  1/8!
+    pc = fmaf(pc, r2, -1.38888889e-3f);     // -1/6!
+    pc = fmaf(pc, r2, 4.16666667e-2f);      //  1/4!
+    pc = fmaf(pc, r2, -0.5f);               // -1/2!
+    const float cr = fmaf(pc, r2, 1.0f);
+    const int q = (int)(k - 4.0 * floor(k * 0.25));  // k mod 4, defined for any k
+    // x = k pi/2 + r: rotate (cos r, sin r) by q quarter turns
+    const float s0 = (q & 1) ? cr : sr, c0 = (q & 1) ? sr : cr;
+    s = (q & 2) ? -s0 : s0;
+    c = ((q + 1) & 2) ? -c0 : c0;
 }
 
 // Factored rotation exp(-i b X) / f on the pair (a, b'):
