@@ -1,0 +1,39 @@
+"""Host code under AddressSanitizer and UndefinedBehaviorSanitizer: the pass
+planner over every size and cap, and the L-BFGS driver on Rosenbrock and on
+objectives that fail or stop.  Built with the host compiler only (no GPU code)."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2407_13012_amd", "csrc")
+HOST = os.path.join(ROOT, "tests", "host")
+ROCM_INCLUDE = "/opt/rocm/include"
+FLAGS = ["-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+
+def _build_and_run(tmp_path, name, sources, extra):
+    exe = str(tmp_path / name)
+    cmd = ["g++", *FLAGS, *extra, "-I", CSRC, "-I", os.path.join(ROOT, "include"), *sources, "-o", exe]
+    subprocess.run(cmd, check=True, capture_output=True, timeout=300)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    return out.stdout
+
+
+@pytest.mark.skipif(shutil.which("g++") is None or not os.path.isdir(ROCM_INCLUDE),
+                    reason="needs g++ and the HIP headers")
+def test_planner_under_sanitizers(tmp_path):
+    out = _build_and_run(tmp_path, "plan_check",
+                         [os.path.join(HOST, "plan_check.cpp"), os.path.join(CSRC, "plan.cpp")],
+                         ["-D__HIP_PLATFORM_AMD__", "-I", ROCM_INCLUDE])
+    assert "plans ok" in out
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_lbfgs_under_sanitizers(tmp_path):
+    out = _build_and_run(tmp_path, "lbfgs_check",
+                         [os.path.join(HOST, "lbfgs_check.cpp"), os.path.join(CSRC, "lbfgs.cpp")], [])
+    assert "lbfgs ok" in out
