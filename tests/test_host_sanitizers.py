@@ -1,6 +1,7 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer: the pass
-planner over every size and cap, and the L-BFGS driver on Rosenbrock and on
-objectives that fail or stop.  Built with the host compiler only (no GPU code)."""
+planner over every size and cap, the L-BFGS driver on Rosenbrock and on
+objectives that fail or stop, and the CPU oracle's routines on small instances.
+Built with the host compilers only (no GPU code)."""
 import os
 import shutil
 import subprocess
@@ -37,3 +38,16 @@ def test_lbfgs_under_sanitizers(tmp_path):
     out = _build_and_run(tmp_path, "lbfgs_check",
                          [os.path.join(HOST, "lbfgs_check.cpp"), os.path.join(CSRC, "lbfgs.cpp")], [])
     assert "lbfgs ok" in out
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_oracle_under_sanitizers(tmp_path):
+    exe = str(tmp_path / "oracle_check")
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", os.path.join(HOST, "oracle_check.c"),
+           os.path.join(ROOT, "oracle", "qaoa_oracle.c"), "-lm", "-o", exe]
+    subprocess.run(cmd, check=True, capture_output=True, timeout=300)
+    env = dict(os.environ, OMP_NUM_THREADS="2")
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "oracle ok" in out.stdout
