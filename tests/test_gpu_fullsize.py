@@ -101,6 +101,8 @@ def test_block_qubo_complex64_n32(block_case):
     inst, gamma, beta, (E_ref, dg_ref, db_ref, _) = block_case
     with H(inst, "c64") as q:
         E, dg, db = q.gradient(gamma, beta)
+        E2, dg2, db2 = q.gradient(gamma, beta)
+    assert E == E2 and np.array_equal(dg, dg2) and np.array_equal(db, db2)  # fixed-order sums
     gscale = max(np.abs(np.concatenate([dg_ref, db_ref])).max(), 1.0)
     assert abs(E - E_ref) / max(abs(E_ref), 1.0) <= 1e-4
     assert np.abs(np.concatenate([dg - dg_ref, db - db_ref])).max() / gscale <= 1e-4
