@@ -34,10 +34,12 @@ DEPTHS = (4, 6, 8, 10)
 
 
 def device_key() -> str:
+    """Architecture and CU count (the marketing name depends on the host's
+    device-id tables, so it is left out)."""
     import torch
     props = torch.cuda.get_device_properties(torch.cuda.current_device())
-    arch = getattr(props, "gcnArchName", "")
-    return f"{props.name}|{arch}|cu{props.multi_processor_count}"
+    arch = getattr(props, "gcnArchName", "").split(":")[0]
+    return f"{arch}|cu{props.multi_processor_count}"
 
 
 def batch_key(graphs, p: int) -> str:
