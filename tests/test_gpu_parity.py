@@ -312,8 +312,8 @@ def test_sample_errors():
 # complex64 tiles hold 2^13 amplitudes: n = 12 is a partial tile, 13 one full
 # tile, 14 a 13-qubit pass plus a one-qubit pass, 24 three passes per layer
 # (both layer-boundary sweeps at p = 3)
-@pytest.mark.parametrize("n,p", [(6, 2), (12, 3), (13, 2), (14, 3), (15, 1), (16, 4), (17, 3), (18, 2),
-                                 (19, 3), (21, 4), (22, 1), (23, 2), (24, 3)])
+@pytest.mark.parametrize("n,p", [(6, 2), (9, 1), (12, 3), (13, 1), (13, 2), (14, 3), (15, 1), (16, 4), (17, 3),
+                                 (18, 2), (19, 3), (21, 4), (22, 1), (23, 2), (24, 3)])
 def test_complex64_against_fp64_oracle(n, p):
     inst = mk("er", n, 400 + n)
     C = oracle.cost_of(inst)
