@@ -585,6 +585,13 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
     double accE = 0.0, accB = 0.0, accG = 0.0;
     const V zero = {(R)0, (R)0};
 
+    // The single-group sweeps raise the wave priority while their loads are
+    // issued, so that a workgroup starting a tile gets its loads in flight ahead
+    // of the arithmetic of the other workgroup on the CU (measured: forward
+    // 26.9 vs 27.8 ms, backward 43 vs 44 ms at n = 32; the layer-boundary
+    // sweeps, whose arithmetic dominates, are faster without it).
+    constexpr bool kPrio = MODE != kBwdFuse;
+    if constexpr (kPrio) __builtin_amdgcn_s_setprio(2);
     // All global loads of the pass are issued up front (cost entries first);
     // loads placed after the arithmetic were found to serialise with it.
     constexpr bool TURN = MODE == kTurn || MODE == kTurnPhase;
@@ -620,6 +627,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
 #pragma unroll
             for (int r = 0; r < NR; ++r) v[r] = VA(r) ? ld(&psi[ZA(r)], strm) : zero;
         }
+        if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
         if (phaseIn) {
 #pragma unroll
             for (int r = 0; r < NR; ++r)
@@ -750,6 +758,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
             f[r] = ok ? ld(&psi[ZA(r)], strm) : zero;
             l[r] = ok ? ld(&lam[ZA(r)], strm) : zero;
         }
+        if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
         const R mb = (R)a.mul_b;
         const double f2 = a.fac_b * a.fac_b;
         double sig2 = 1.0;
