@@ -101,7 +101,13 @@ qaoa_status qaoa_create_qubo(int32_t n, int64_t m, const int32_t *pairs, const d
 qaoa_status qaoa_create_poly(int32_t n, int64_t L, const uint64_t *masks, const double *w,
                              double offset, int32_t precision, void *stream, qaoa_handle *out);
 
-/* Release every device buffer and the private stream.  NULL is a no-op. */
+/*
+ * Release the handle (Sec. IV-B: the handle owns the state, the cost array, a
+ * stream and every buffer allocated later): waits for the handle's stream,
+ * frees every device buffer through the allocator the handle was created with
+ * and destroys the private stream (a caller's stream is left alone).  Valid
+ * after QAOA_ERR_DEVICE.  NULL is a no-op.
+ */
 qaoa_status qaoa_destroy(qaoa_handle h);
 
 /* Report n and the precision of a handle (either output pointer may be NULL). */
@@ -115,7 +121,12 @@ qaoa_status qaoa_get_info(qaoa_handle h, int32_t *n, int32_t *precision);
  */
 qaoa_status qaoa_cost_diagonal(qaoa_handle h, double *out, int32_t out_is_device);
 
-/* Minimum and maximum of the cost diagonal (for approximation ratios). */
+/*
+ * Minimum and maximum of the cost diagonal of Eq. (2) (Sec. IV-A), reduced on
+ * the device over all 2^n entries (for approximation ratios E / C_max).  The
+ * values are cached in the handle after the first call.  Synchronises the
+ * stream.  Errors: INVALID_ARGUMENT (NULL outputs), DEVICE.
+ */
 qaoa_status qaoa_cost_extrema(qaoa_handle h, double *cmin, double *cmax);
 
 /*
@@ -172,7 +183,7 @@ qaoa_status qaoa_sample(qaoa_handle h, int64_t shots, uint64_t seed, uint64_t *z
                         int32_t out_is_device);
 
 /*
- * Limited-memory BFGS (Sec. V-C offers L-BFGS natively; Liu & Nocedal 1989):
+ * Limited-memory BFGS (Sec. V-B offers L-BFGS natively; Liu & Nocedal 1989):
  * two-loop recursion with m stored correction pairs and a strong-Wolfe line
  * search (c1 = 1e-4, c2 = 0.9).  Every trial point costs one evaluation.
  */
@@ -246,7 +257,7 @@ qaoa_status qaoa_pass_plan(int32_t n, int32_t precision, int32_t cap, int32_t *n
 
 /*
  * Batched engine: many small weighted MaxCut instances, each optimised with
- * Adam on its 2p angles, in one persistent launch (Sec. V-C: parameter
+ * Adam on its 2p angles, in one persistent launch (Sec. V-B: parameter
  * optimisation driven by the simulator's gradients; here every instance's loop
  * runs on the device).
  *
@@ -408,10 +419,16 @@ typedef struct {
  */
 qaoa_status qaoa_set_allocator(const qaoa_allocator *a);
 
-/* Static English description of a status code. */
+/*
+ * Static English description of a status code.  Together with
+ * qaoa_last_error_message this is how the boundary reports errors: no call
+ * throws or aborts, each returns a status (the handle of Sec. IV-B is the
+ * only state a call keeps).
+ */
 const char *qaoa_status_string(qaoa_status s);
 
-/* Message of the last failing call on this thread ("" if none). */
+/* Message of the last failing call on this thread ("" if none); valid until
+ * the next failing call on the same thread. */
 const char *qaoa_last_error_message(void);
 
 #ifdef __cplusplus

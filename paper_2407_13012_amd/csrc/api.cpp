@@ -448,7 +448,8 @@ qaoa_status create_common(int32_t n, int32_t precision, void *stream, qaoa_handl
     return QAOA_OK;
 }
 
-// Copies host term arrays to the device, builds the cost diagonal, frees the copies.
+// Copies host term arrays to the device (through the handle's allocator),
+// builds the cost diagonal, frees the copies once the stream has drained.
 template <typename Launch>
 qaoa_status build_cost(qaoa_handle h, const std::vector<std::pair<const void *, size_t>> &arrays,
                        Launch launch)
@@ -457,7 +458,12 @@ qaoa_status build_cost(qaoa_handle h, const std::vector<std::pair<const void *, 
     qaoa_status st = QAOA_OK;
     for (size_t i = 0; i < arrays.size() && st == QAOA_OK; ++i) {
         if (!arrays[i].first || arrays[i].second == 0) continue;
-        hipError_t e = hipMalloc(&dev[i], arrays[i].second);
+        hipError_t e = dev_alloc(h, &dev[i], arrays[i].second);
+        if (e == hipErrorOutOfMemory) {
+            dev[i] = nullptr;
+            st = fail(QAOA_ERR_OUT_OF_MEMORY, "term upload buffer allocation failed");
+            break;
+        }
         if (e == hipSuccess)
             e = hipMemcpyAsync(dev[i], arrays[i].first, arrays[i].second, hipMemcpyHostToDevice,
                                h->stream);
@@ -467,9 +473,10 @@ qaoa_status build_cost(qaoa_handle h, const std::vector<std::pair<const void *, 
         hipError_t e = launch(dev);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) st = device_fail(h, "cost diagonal", e);
+    } else {
+        (void)hipStreamSynchronize(h->stream);  // copies already queued must finish before the frees
     }
-    for (void *p : dev)
-        if (p) (void)hipFree(p);
+    for (size_t i = 0; i < dev.size(); ++i) dev_free(h, dev[i], arrays[i].second);
     return st;
 }
 
@@ -835,6 +842,12 @@ qaoa_status qaoa_sample(qaoa_handle h, int64_t shots, uint64_t seed, uint64_t *z
         if (cost)
             HIPCHECK(h, hipMemcpyAsync(cost, dc, (size_t)shots * 8, hipMemcpyDeviceToHost, h->stream));
         HIPCHECK(h, hipStreamSynchronize(h->stream));
+        // a large staging area is given back; later calls allocate what they need
+        if (stage * sizeof(double) > (64ull << 20)) {
+            dev_free(h, h->parts, h->parts_cap * sizeof(double));
+            h->parts = nullptr;
+            h->parts_cap = 0;
+        }
     }
     return QAOA_OK;
 }

@@ -441,7 +441,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_final(const double *in, uint6
     if (blockIdx.x == 0 && threadIdx.x == 0) out[count] = tot[nchunks];
 }
 
-// One thread per shot: u -> target t = u * total, binary search over the
+// One thread per shot (grid-stride): u -> target t = u * total, binary search over the
 // sub-block prefix, then a sequential scan inside the sub-block for the first
 // z whose cumulative mass exceeds t.  A zero-probability z never satisfies the
 // test (its cumulative mass equals its predecessor's), so it is never returned.
@@ -452,32 +452,33 @@ __global__ __launch_bounds__(kThreads) void k_shots(const typename Tr<R>::V *psi
                                                     int64_t shots, uint64_t seed, uint64_t *zout,
                                                     double *cout)
 {
-    const uint64_t s = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (s >= (uint64_t)shots) return;
     const double T = pre[nsub];
-    const double t = philox_uniform53(seed, s) * T;
-    uint64_t lo = 0, hi = nsub - 1;  // smallest j with pre[j+1] > t
-    while (lo < hi) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        if (pre[mid + 1] > t) hi = mid;
-        else lo = mid + 1;
-    }
-    const uint64_t z0 = lo << sbits;
-    const uint64_t zend = min(N, z0 + (1ull << sbits));
-    double acc = pre[lo];
-    uint64_t zsel = ~0ull, zlast = z0;
-    for (uint64_t z = z0; z < zend; ++z) {
-        const double pz = norm2(psi[z]);
-        if (pz > 0.0) zlast = z;
-        acc += pz;
-        if (acc > t) {
-            zsel = z;
-            break;
+    const uint64_t stride = (uint64_t)gridDim.x * kThreads;
+    for (uint64_t s = (uint64_t)blockIdx.x * kThreads + threadIdx.x; s < (uint64_t)shots; s += stride) {
+        const double t = philox_uniform53(seed, s) * T;
+        uint64_t lo = 0, hi = nsub - 1;  // smallest j with pre[j+1] > t
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (pre[mid + 1] > t) hi = mid;
+            else lo = mid + 1;
         }
+        const uint64_t z0 = lo << sbits;
+        const uint64_t zend = min(N, z0 + (1ull << sbits));
+        double acc = pre[lo];
+        uint64_t zsel = ~0ull, zlast = z0;
+        for (uint64_t z = z0; z < zend; ++z) {
+            const double pz = norm2(psi[z]);
+            if (pz > 0.0) zlast = z;
+            acc += pz;
+            if (acc > t) {
+                zsel = z;
+                break;
+            }
+        }
+        if (zsel == ~0ull) zsel = zlast;  // rounding left t at the sub-block's end
+        zout[s] = zsel;
+        if (cout) cout[s] = (double)C[zsel];
     }
-    if (zsel == ~0ull) zsel = zlast;  // rounding left t at the sub-block's end
-    zout[s] = zsel;
-    if (cout) cout[s] = (double)C[zsel];
 }
 
 // Workgroups of a cost-diagonal launch: one per 4096 entries, at most 2^20.
@@ -687,7 +688,8 @@ hipError_t launch_shots(bool c64, const void *psi, const void *C, int n, int sbi
                         uint64_t *z, double *cost, hipStream_t s)
 {
     const uint64_t N = 1ull << n;
-    const unsigned nb = (unsigned)(((uint64_t)shots + kThreads - 1) / kThreads);
+    // one thread per shot up to 2^20 workgroups; beyond that each thread takes several
+    const unsigned nb = grid_for((uint64_t)shots);
     if (c64)
         hipLaunchKernelGGL(k_shots<float>, dim3(nb), dim3(kThreads), 0, s, (const Tr<float>::V *)psi,
                            (const float *)C, N, sbits, pre, nsub, shots, seed, z, cost);

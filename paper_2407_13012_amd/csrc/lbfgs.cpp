@@ -1,4 +1,4 @@
-// Limited-memory BFGS (the optimiser the paper offers natively, Sec. V-C;
+// Limited-memory BFGS (the optimiser the paper offers natively, Sec. V-B;
 // Liu & Nocedal 1989) for the QAOA angles.
 //
 // Written from the textbook description (Nocedal & Wright, Numerical

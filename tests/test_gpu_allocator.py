@@ -24,10 +24,14 @@ def test_torch_allocator_holds_buffers_and_results_match():
         E0, dg0, db0 = ref.gradient(g, b)
     torch.cuda.synchronize()
     before = torch.cuda.memory_allocated()
+    nalloc0 = torch.cuda.memory_stats()["allocation.all.allocated"]
     with use_torch_allocator():
         h = QaoaHandle.from_instance(inst)
     during = torch.cuda.memory_allocated()
     assert during - before >= (1 << 20) * 24  # state + cost diagonal of n = 20
+    # state, cost diagonal, partials, results, and the two term arrays uploaded
+    # to build the diagonal (edges, weights): all through the allocator
+    assert torch.cuda.memory_stats()["allocation.all.allocated"] - nalloc0 >= 6
     E1, dg1, db1 = h.gradient(g, b)
     assert torch.cuda.memory_allocated() - before >= (1 << 20) * 40  # plus the adjoint vector
     h.close()

@@ -186,6 +186,17 @@ def test_batch_family_sampled_full_run():
         assert abs(e1[i] - oe1) <= 1e-7 * max(1.0, float(np.abs(g.weight_array()).sum()))
 
 
+def test_batch_largest_sizes_match_oracle():
+    """The family's largest instances (n = 18, 19, 20: 2^18..2^20 amplitudes,
+    plans whose high passes rotate page-crossing qubits >= 17) next to small
+    ones in one launch, three Adam steps at p = 4, against the oracle."""
+    graphs = family([20, 18, 11, 19, 13, 20], seed=81)
+    p, steps = 4, 3
+    g0, b0 = start_angles(graphs, p, seed=8)
+    res = run_batch(graphs, p, g0, b0, steps=steps, workgroups=4)
+    check_against_oracle(graphs, p, g0, b0, res, steps=steps)
+
+
 def test_batch_matches_single_instance_library():
     """The batched engine's Adam trajectory equals Adam driven from the host by
     the single-instance library's gradients (same updates, gradients agreeing to

@@ -2,15 +2,14 @@
 stored-state adjoint gradient handles in host memory: 7 x 4 GiB), in the same
 three-sweep-per-layer pass structure as n = 32, against the oracle element by
 element: E within 1e-10 * sum|w|, gradients within 1e-8; complex64 within
-1e-4 relative.  Also a throughput floor at n = 32 (0.70 of the HBM roofline
-under the pass byte model p(6 P s + 2c) + c - 2s per amplitude) as a
-regression check."""
+1e-4 relative.  Also a throughput floor at n = 32 (a time bound and the
+fraction of the HBM peak by the bytes the passes move) as a regression
+check."""
 import time
 
 import numpy as np
 import pytest
 
-import oracle
 import qaoa_inputs as qi
 
 pytestmark = pytest.mark.gpu
@@ -24,13 +23,9 @@ def _gpu():
 
 
 @pytest.fixture(scope="module")
-def family28():
-    w = qi.workload_qubo32(28)
-    inst = w["instance"]
-    C = oracle.cost_of(inst)
-    E, dg, db = oracle.gradient(inst.n, C, w["gamma"], w["beta"])
-    scale = float(np.abs(inst.J).sum() + np.abs(inst.h).sum())
-    return inst, w["gamma"], w["beta"], (E, dg, db), scale
+def family28(qubo28_reference):
+    r = qubo28_reference
+    return r["inst"], r["gamma"], r["beta"], (r["E"], r["dg"], r["db"]), r["scale"]
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
@@ -53,6 +48,9 @@ def test_qubo_family_n28_gradient(family28, prec):
 
 
 def test_n32_gradient_throughput_floor():
+    """Regression floor on the headline step: at most 600 ms per E+G, and the
+    bytes the passes actually move (the library's own per-launch byte count,
+    about 616 B per amplitude) at no less than 0.55 of the 8 TB/s peak."""
     import torch
     from paper_2407_13012_amd import QaoaHandle
     free, _ = torch.cuda.mem_get_info()
@@ -62,10 +60,14 @@ def test_n32_gradient_throughput_floor():
     with QaoaHandle.from_instance(w["instance"]) as q:
         q.gradient(w["gamma"], w["beta"])
         torch.cuda.synchronize()
+        q.profile_enable(True)
         t0 = time.perf_counter()
         for _ in range(3):
             q.gradient(w["gamma"], w["beta"])
         dt = (time.perf_counter() - t0) / 3
-    model_bytes = 888 * 2.0 ** 32  # p(6 P s + 2 c) + c - 2 s with P = 3, s = 16, c = 8
-    frac = model_bytes / dt / 8e12
-    assert frac >= 0.70, f"{dt * 1e3:.1f} ms per E+G = {frac:.3f} of the HBM roofline"
+        moved = sum(v[2] for v in q.profile_read().values()) / 3
+        q.profile_enable(False)
+    frac = moved / dt / 8e12
+    print(f"n=32 E+G: {dt * 1e3:.1f} ms, {moved / 2.0 ** 32:.0f} B/amp moved, {frac:.3f} of 8 TB/s", flush=True)
+    assert dt <= 0.600, f"{dt * 1e3:.1f} ms per E+G"
+    assert frac >= 0.55, f"{frac:.3f} of the HBM peak by moved bytes"

@@ -43,35 +43,59 @@ def test_lbfgs_iterates_match_oracle_small():
         assert E > tE[0]
 
 
-def test_lbfgs_regular26_c128_and_c64():
-    """3-regular MaxCut n=26, w ~ U[0,1], p=6, 200 L-BFGS iterations from the noisy
-    ramp in complex128 and complex64; oracle E and gradient at the start and at
-    each precision's final iterate."""
+RUNS = {}
+
+
+@pytest.fixture(scope="module")
+def regular26():
     w = qi.workload_regular26()
-    g_inst = w["instance"]
-    C = oracle.cost_of(g_inst)
-    out = {}
-    for prec in ["c128", "c64"]:
-        with H(g_inst, prec) as q:
-            g, b, E, it, ev, tx, tE = q.optimize(w["gamma"], w["beta"], max_iter=200, gtol=1e-7,
-                                                 max_evals=400, trace=True)
-            _, dg, db = q.gradient(g, b)
-        out[prec] = (g, b, E, it, ev, tE, dg, db)
+    return w, oracle.cost_of(w["instance"])
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_lbfgs_regular26_iterates_match_oracle(regular26, prec):
+    """3-regular MaxCut n=26, w ~ U[0,1], p=6, 200 L-BFGS iterations from the
+    noisy ramp.  The trajectory itself has no oracle (parity unpinned along the
+    path); the oracle's E and gradient are evaluated at the GPU's own iterates
+    0, 20, 40, ..., 200 and at the returned optimum, and compared with the GPU's
+    values there: complex128 to 1e-10 sum|w| (E) and 1e-8 (gradient), complex64
+    to 1e-4 relative (E) and 1e-4 |g_k| + 1e-5 max|g| per component."""
+    w, C = regular26
+    inst = w["instance"]
+    p = len(w["gamma"])
+    wsum = float(np.abs(inst.weight_array()).sum())
+    with H(inst, prec) as q:
+        g, b, E, it, ev, tx, tE = q.optimize(w["gamma"], w["beta"], max_iter=200, gtol=1e-7,
+                                             max_evals=400, trace=True)
         print(f"{prec}: iterations {it}, evaluations {ev}, E {tE[0]:.9f} -> {E:.9f}", flush=True)
-    E0_ref = oracle.gradient(g_inst.n, C, w["gamma"], w["beta"])[0]
-    assert abs(out["c128"][5][0] - E0_ref) < 1e-10 * g_inst.m
-    assert abs(out["c64"][5][0] - E0_ref) / abs(E0_ref) < 1e-4
-    for prec, tol in [("c128", None), ("c64", 1e-4)]:
-        g, b, E, it, ev, tE, dg, db = out[prec]
-        E_ref, dg_ref, db_ref = oracle.gradient(g_inst.n, C, g, b)
-        gscale = max(1.0, np.abs(np.concatenate([dg_ref, db_ref])).max())
-        if tol is None:
-            assert abs(E - E_ref) < 1e-10 * g_inst.m
-            assert np.max(np.abs(np.concatenate([dg - dg_ref, db - db_ref]))) < 1e-8
+        pins = list(range(0, it + 1, 20))
+        points = [(k, tx[k, :p], tx[k, p:], tE[k]) for k in pins] + [("opt", g, b, E)]
+        gpu = [q.gradient(gk, bk) for _, gk, bk, _ in points]
+    assert it >= 20 and E > tE[0] + 0.1
+    assert np.all(np.diff(tE[:it + 1]) >= -1e-9 * wsum)     # maximisation: E never decreases
+    worst = {"E": 0.0, "grad": 0.0}
+    for (k, gk, bk, Ek), (Eg, dg, db) in zip(points, gpu):
+        E_ref, dg_ref, db_ref = oracle.gradient(inst.n, C, gk, bk)
+        gr = np.concatenate([dg_ref, db_ref])
+        d = np.abs(np.concatenate([dg, db]) - gr)
+        if prec == "c128":
+            assert abs(Ek - E_ref) <= 1e-10 * wsum and abs(Eg - E_ref) <= 1e-10 * wsum, (k, Ek, Eg, E_ref)
+            assert d.max() <= 1e-8, (k, d.max())
         else:
-            assert abs(E - E_ref) / abs(E_ref) < tol
-            assert np.max(np.abs(np.concatenate([dg - dg_ref, db - db_ref]))) / gscale < tol
-        assert E > tE[0] + 0.1
-    # both precisions reach the same local optimum (approximation ratio within 1e-4)
-    cmax = C.max()
-    assert abs(out["c128"][2] - out["c64"][2]) / cmax < 1e-4
+            gmax = float(np.abs(gr).max())
+            assert abs(Ek - E_ref) <= 1e-4 * abs(E_ref) and abs(Eg - E_ref) <= 1e-4 * abs(E_ref), (k, Ek, E_ref)
+            assert np.all(d <= 1e-4 * np.abs(gr) + 1e-5 * gmax), (k, d, gr)
+        worst["E"] = max(worst["E"], abs(Eg - E_ref) / abs(E_ref))
+        worst["grad"] = max(worst["grad"], float(d.max() / np.abs(gr).max()))
+    print(f"{prec}: pinned iterates {pins} + optimum; worst relative error E {worst['E']:.2e}, "
+          f"gradient {worst['grad']:.2e}", flush=True)
+    RUNS[prec] = (E, C.max())
+
+
+def test_lbfgs_regular26_precisions_reach_same_ratio():
+    """Both precisions end at the same local optimum: approximation ratios E / C_max within 1e-4."""
+    if set(RUNS) != {"c128", "c64"}:
+        pytest.skip("needs both L-BFGS runs of this module")
+    (E128, cmax), (E64, _) = RUNS["c128"], RUNS["c64"]
+    assert abs(E128 - E64) / cmax < 1e-4

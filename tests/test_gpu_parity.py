@@ -307,6 +307,40 @@ def test_sample_errors():
         assert z.size == 0
 
 
+def test_sample_beyond_one_grid_pass():
+    """2^28 + 7 shots: more than one launch of 2^20 workgroups x 256 threads
+    covers, so threads take several shots each.  The leading shots equal a
+    small call's (same counters), the last ones are the smallest z whose
+    cumulative probability in the exported state exceeds the oracle's uniform
+    for that shot times the total, and every returned z is a valid index."""
+    import torch
+    n = 5
+    inst = mk("er", n, 77)
+    gamma, beta = [0.4, 0.9], [0.7, 0.2]
+    shots = (1 << 28) + 7
+    with H(inst) as q:
+        psi = q.statevector(gamma, beta)
+        z_small, _ = q.sample(1000, 11)
+        zt = torch.empty(shots, dtype=torch.int64, device="cuda")
+        q.sample(shots, 11, z_out=zt)
+        torch.cuda.synchronize()
+        head = zt[:1000].cpu().numpy().astype(np.uint64)
+        tail = zt[-7:].cpu().numpy()
+        top = int(zt.max().item())
+        del zt
+        torch.cuda.empty_cache()
+    assert np.array_equal(head, z_small)
+    assert top < (1 << n)
+    prob = np.abs(psi) ** 2
+    S = np.cumsum(prob)
+    for k, zk in enumerate(tail):
+        u = oracle.uniform53(11, shots - 7 + k)
+        # smallest z whose cumulative probability exceeds u * total (the GPU's
+        # prefix sums round differently, which matters only within ~1e-16 of a boundary)
+        want = int(np.searchsorted(S, u * S[-1], side="right"))
+        assert zk == want and prob[zk] > 0, (k, zk, want)
+
+
 # ---------------------------------------------------------------- complex64
 
 # complex64 tiles hold 2^13 amplitudes: n = 12 is a partial tile, 13 one full

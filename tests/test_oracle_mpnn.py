@@ -1,7 +1,8 @@
 """Pins of the warm-start network's CPU oracle (oracle/mpnn.py) to facts that
 do not depend on it: central finite differences of its own loss (the backward
 pass), torch's bfloat16 conversion (the rounding), a closed form for zero
-message-passing weights, and invariances of the definition (vertex relabelling,
+message-passing weights (the mean readout), the one-node recursion of a
+vertex-transitive graph (the weighted aggregation), and invariances of the definition (vertex relabelling,
 batch composition)."""
 import numpy as np
 import pytest
@@ -78,6 +79,53 @@ def test_zero_message_weights_closed_form():
     for gi in range(len(graphs)):
         np.testing.assert_allclose(gamma[gi], i + Y[:p], rtol=0, atol=1e-15)
         np.testing.assert_allclose(beta[gi], 1 - i + Y[p:], rtol=0, atol=1e-15)
+
+
+def test_readout_is_the_node_mean():
+    """With every message-passing weight zero each node ends layer 3 at
+    ReLU(b_2), so the readout is ReLU(b_2) itself under mean pooling (n times
+    it under sum pooling) and Y = W_h2 ReLU(W_h1 ReLU(b_2) + b_h1) + b_h2 for
+    graphs of every size."""
+    p = 3
+    graphs = small_graphs(3) + [qi.MaxCut(n=1, edges=np.zeros((0, 2), np.int32), weights=None)]
+    P = mpnn.unflatten(qi.mpnn_init_params(p, 17), p)
+    for l in range(3):
+        P[f"W{l}"][:] = 0.0
+    rng = np.random.default_rng(4)
+    P["b2"] = rng.normal(0, 0.5, P["b2"].shape)   # about half the units active
+    theta = mpnn.flatten(P, p)
+    gamma, beta = mpnn.forward(theta, graphs, p)
+    g = np.maximum(P["b2"], 0.0)
+    Y = P["Wh2"] @ np.maximum(P["Wh1"] @ g + P["bh1"], 0.0) + P["bh2"]
+    i = np.arange(1, p + 1) / p
+    for gi in range(len(graphs)):
+        np.testing.assert_allclose(gamma[gi], i + Y[:p], rtol=0, atol=1e-13)
+        np.testing.assert_allclose(beta[gi], 1 - i + Y[p:], rtol=0, atol=1e-13)
+
+
+def test_vertex_transitive_graph_reduces_to_one_node():
+    """On a cycle C_n with one weight w on every edge all nodes are alike, so
+    H stays equal across nodes and (A H)_v = 2 w h: each layer is the
+    one-vector recursion h' = ReLU(W_self h + 2 w W_msg h + b), with the input
+    x = (2/8, 2w/8, 1, 2w^2/8, 0, ...).  This pins the weighted, symmetric
+    aggregation and the split of W_l into its self and message halves."""
+    p = 2
+    P = mpnn.unflatten(qi.mpnn_init_params(p, 23), p)
+    theta = mpnn.flatten(P, p)
+    for n, w in ((5, 0.7), (8, -0.4)):
+        e = np.array([[k, (k + 1) % n] for k in range(n)], dtype=np.int32)
+        cyc = qi.MaxCut(n=n, edges=e, weights=np.full(n, w))
+        gamma, beta = mpnn.forward(theta, [cyc], p)
+        h = np.zeros(mpnn.FIN)
+        h[:4] = (2 / 8, 2 * w / 8, 1.0, 2 * w * w / 8)
+        for l in range(3):
+            W = P[f"W{l}"]
+            d = W.shape[1] // 2
+            h = np.maximum(W[:, :d] @ h + 2 * w * (W[:, d:] @ h) + P[f"b{l}"], 0.0)
+        Y = P["Wh2"] @ np.maximum(P["Wh1"] @ h + P["bh1"], 0.0) + P["bh2"]
+        i = np.arange(1, p + 1) / p
+        np.testing.assert_allclose(gamma[0], i + Y[:p], rtol=0, atol=1e-12)
+        np.testing.assert_allclose(beta[0], 1 - i + Y[p:], rtol=0, atol=1e-12)
 
 
 @pytest.mark.parametrize("bf16_ops", [False, True])
