@@ -214,7 +214,8 @@ def warmstart_leg(count: int, log) -> dict:
     """Time-to-ratio of learned vs plain starts: L-BFGS (one qaoa_gradient per
     evaluation) from the linear ramp and from the trained network's angles on
     held-out ER(24, 0.5) graphs, p = 8; evaluations and wall time until the
-    plain run's final approximation ratio minus 0.005 is reached."""
+    plain run's final approximation ratio minus 0.005 is reached (the plain run
+    goes on to convergence, which sets that target; the learned run stops there)."""
     import numpy as np
 
     import qaoa_inputs as qi
@@ -224,30 +225,87 @@ def warmstart_leg(count: int, log) -> dict:
         return {"skipped": "no trained parameters"}
     params = np.load(WARMSTART_PARAMS, allow_pickle=False)
     graphs = qi.warmstart_eval_graphs(count)
-    res = ws.evaluate(params, graphs, 8, log=log)
+    res = ws.evaluate(params, graphs, 8, learned_until_target=True, log=log)
     res.pop("rows")
     return res
 
 
-def cpu_baseline(inst_fn, p_n, full_n, gamma, beta, batch_sample: int = 64):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ONE_THREAD_SNIPPET = """
+import sys, time
+sys.path.insert(0, {root!r})
+import oracle, qaoa_inputs as qi
+w = qi.workload_qubo32({n})
+inst = w["instance"]
+C = oracle.cost_of(inst)
+t0 = time.perf_counter()
+oracle.gradient(inst.n, C, w["gamma"], w["beta"])
+print(time.perf_counter() - t0, oracle.num_threads())
+"""
+
+
+def one_thread_oracle_seconds(n: int):
+    """One oracle E+G of the n-variable member of the headline family in a child
+    process restricted to one OpenMP thread: (seconds, threads used)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", _ONE_THREAD_SNIPPET.format(root=ROOT, n=n)],
+                         env=env, capture_output=True, text=True, timeout=600, check=True)
+    dt, thr = out.stdout.split()[-2:]
+    return float(dt), int(thr)
+
+
+def cpu_baseline(inst_fn, sample_n, full_n, gamma, beta, batch_sample: int = 64,
+                 slope_n: int = 26, one_thread_n: int = 22):
+    """The CPU oracle (OpenMP over the host's cores) on bounded samples of the
+    workloads: the headline E+G at n = sample_n (and slope_n, to show the 2^n
+    scaling the extrapolation assumes), scaled by 2^(full_n - sample_n); one
+    thread at n = one_thread_n; the two smaller configurations in full; 64
+    graphs of the batched family."""
     import numpy as np
 
     import oracle
     import qaoa_inputs as qi
-    inst = inst_fn(p_n)["instance"]
-    C = oracle.cost_of(inst)
-    t0 = time.perf_counter()
-    oracle.gradient(p_n, C, gamma, beta)
-    dt = time.perf_counter() - t0
-    scale = 2.0 ** (full_n - p_n)
+
+    def timed(n):
+        inst = inst_fn(n)["instance"]
+        C = oracle.cost_of(inst)
+        t0 = time.perf_counter()
+        oracle.gradient(n, C, gamma, beta)
+        return time.perf_counter() - t0
+
+    dt = timed(sample_n)
+    scale = 2.0 ** (full_n - sample_n)
     out = {
         "value": 1.0 / (dt * scale),
         "unit": "grad_evals/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": (f"one oracle E+G ({dt:.2f} s) of the n={p_n} member of the same QUBO family "
-                   f"(p={len(gamma)}), scaled by 2^{full_n - p_n} to n={full_n} (extrapolated)"),
+        "sample": (f"one oracle E+G ({dt:.2f} s) of the n={sample_n} member of the same QUBO family "
+                   f"(p={len(gamma)}), scaled by 2^{full_n - sample_n} to n={full_n} (extrapolated)"),
+        "cpu_model": cpu_model(),
+        "logical_cpus_visible": len(os.sched_getaffinity(0)),
+        f"qubo{sample_n}_grad_s": dt,
     }
+    if slope_n and slope_n != sample_n:
+        ds = timed(slope_n)
+        out[f"qubo{slope_n}_grad_s"] = ds
+        out["time_ratio_per_qubit"] = (dt / ds) ** (1.0 / (sample_n - slope_n))
+    if one_thread_n:
+        d1, thr = one_thread_oracle_seconds(one_thread_n)
+        out["single_thread"] = {
+            "value": 1.0 / (d1 * 2.0 ** (full_n - one_thread_n)), "unit": "grad_evals/s", "cores": thr,
+            "sample": (f"one oracle E+G ({d1:.2f} s) at n={one_thread_n}, one OpenMP thread, "
+                       f"scaled by 2^{full_n - one_thread_n} to n={full_n} (extrapolated)")}
     # the two smaller configurations, timed in full: MaxCut ER(12, 0.5) at p = 2 and the
     # n = 26 weighted 3-regular MaxCut at p = 6 (complex128)
     for key, wl in (("maxcut12_p2", qi.workload_small), ("regular26_p6", qi.workload_regular26)):
@@ -280,14 +338,14 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=32)
     ap.add_argument("--precision", default="c128", choices=["c128", "c64"])
-    ap.add_argument("--cpu-sample-n", type=int, default=26)
+    ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--no-warmstart", action="store_true")
-    ap.add_argument("--warmstart-graphs", type=int, default=16)
+    ap.add_argument("--warmstart-graphs", type=int, default=512)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="first run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -447,12 +505,18 @@ def main() -> int:
             "state_bytes": int(N * s), "precision": args.precision,
         },
         "roofline": roofline,
-        # whole E+G against the pass byte model p(6 P s + 2c) + c - 2s per amplitude
-        # with P = ceil(n / kmax) (kmax 13 for 16-byte amplitudes, 14 for 8-byte ones)
-        "step_roofline": {"bound": "hbm", "model_bytes_per_amp": extra["model_bytes_per_amp"],
+        # whole E+G: the bytes its passes actually move (each vector read or written once
+        # per sweep, plus the cost reads) over the step time; the model-equivalent figure
+        # prices the step at the pass model p(6 P s + 2c) + c - 2s per amplitude with
+        # P = ceil(n / kmax) (kmax 13 for 16-byte amplitudes, 14 for 8-byte ones)
+        "step_roofline": {"bound": "hbm",
                           "implemented_bytes_per_amp": extra["implemented_bytes_per_amp"],
-                          "achieved": extra["model_bytes_per_amp"] * N / (ms_per_step * 1e-3) / 1e9,
-                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": extra["model_roofline_frac"]},
+                          "achieved": extra["step_GBps"],
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": extra["step_GBps"] / HBM_PEAK_GBS,
+                          "model_bytes_per_amp": extra["model_bytes_per_amp"],
+                          "model_equivalent_GBps": extra["model_bytes_per_amp"] * N / (ms_per_step * 1e-3) / 1e9,
+                          "model_equivalent_frac": extra["model_roofline_frac"]},
         "cpu_baseline": cpu,
         "extra": extra,
     }

@@ -1,9 +1,14 @@
-"""Build the gfx950 shared library libqaoa.so in-tree with hipcc."""
+"""Build the gfx950 shared library libqaoa.so in-tree with hipcc.
+
+Each source is compiled to an object in parallel, then the objects are linked
+into the shared library (no device code crosses translation units)."""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -12,23 +17,42 @@ SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "batch.hip", "
 ARCH = os.environ.get("QAOA_OFFLOAD_ARCH", "gfx950")
 
 
-def hipcc_command(out: str) -> list[str]:
+def compile_flags() -> list[str]:
     return [
-        "hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+        f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
         # packed fp32 instructions are disabled for every HIP translation unit
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wall", "-Wno-unused-result",
         "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-        *SOURCES, "-o", out,
     ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = hipcc_command(tmp)
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
+    with tempfile.TemporaryDirectory(prefix="qaoa_build_") as tmpd:
+        objs = [os.path.join(tmpd, os.path.basename(s) + ".o") for s in SOURCES]
+        cmds = [["hipcc", *compile_flags(), "-c", s, "-o", o] for s, o in zip(SOURCES, objs)]
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), flush=True)
+
+        def run(c):
+            return subprocess.run(c, capture_output=True, text=True)
+
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            results = list(ex.map(run, cmds))
+        for c, r in zip(cmds, results):
+            if verbose and r.stderr:
+                print(r.stderr, end="", file=sys.stderr, flush=True)
+            if r.returncode != 0:
+                if not verbose:
+                    print(r.stderr, end="", file=sys.stderr, flush=True)
+                raise subprocess.CalledProcessError(r.returncode, c)
+        tmp = LIB + ".tmp"
+        link = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.check_call(link)
     os.replace(tmp, LIB)
     return LIB
 

@@ -107,18 +107,32 @@ def train(graphs, gamma, beta, p: int, epochs: int = 30, batch: int = 256, lr: f
         "best_epoch": best_epoch, "best_val_loss": best_val, "selected": select}
 
 
-def _lbfgs_counted(h: QaoaHandle, x0, p: int, max_iter: int, gtol: float):
-    """L-BFGS on -E from x0; returns (x, E_final, E after every evaluation)."""
-    trace = []
+class _Reached(Exception):
+    """Raised inside an L-BFGS evaluation to stop the run once E reaches its target."""
+
+
+def _lbfgs_counted(h: QaoaHandle, x0, p: int, max_iter: int, gtol: float, stop_at: Optional[float] = None):
+    """L-BFGS on -E from x0.  Returns (E_final, E after every evaluation, seconds
+    from the start to the end of every evaluation).  With stop_at the run ends
+    at the first evaluation whose E reaches it (E_final is then that E)."""
+    trace, times = [], []
+    t0 = time.perf_counter()
 
     def fun(x):
         E, dg, db = h.gradient(x[:p], x[p:])
         trace.append(E)
+        times.append(time.perf_counter() - t0)
+        if stop_at is not None and E >= stop_at:
+            raise _Reached()
         return -E, -np.concatenate([dg, db])
 
-    x, f, _, _ = qaoa_lbfgs_minimize(fun, x0, max_iter=max_iter, gtol=gtol, ftol=1e-12,
-                                     max_evals=4 * max_iter)
-    return x, -f, np.asarray(trace)
+    try:
+        _, f, _, _ = qaoa_lbfgs_minimize(fun, x0, max_iter=max_iter, gtol=gtol, ftol=1e-12,
+                                         max_evals=4 * max_iter)
+        E_final = -f
+    except _Reached:
+        E_final = trace[-1]
+    return E_final, np.asarray(trace), np.asarray(times)
 
 
 def evals_to_reach(trace: np.ndarray, target: float) -> Optional[int]:
@@ -128,8 +142,13 @@ def evals_to_reach(trace: np.ndarray, target: float) -> Optional[int]:
 
 
 def evaluate(params, graphs, p: int, tol: float = 0.005, max_iter: int = 200, gtol: float = 1e-6,
-             log=print) -> Dict:
-    """Plain (ramp) vs learned starts under the same L-BFGS; see the module docstring."""
+             learned_until_target: bool = False, log=print) -> Dict:
+    """Plain (ramp) vs learned starts under the same L-BFGS; see the module docstring.
+
+    The plain run always runs to convergence (its final ratio defines the
+    target).  With learned_until_target the learned run stops at the first
+    evaluation that reaches the target (time-to-ratio); otherwise it also runs
+    to convergence and its final ratio is reported."""
     g_ramp, b_ramp = ramp_angles(1, p)
     x_ramp = np.concatenate([g_ramp[0], b_ramp[0]])
     t0 = time.perf_counter()
@@ -137,36 +156,49 @@ def evaluate(params, graphs, p: int, tol: float = 0.005, max_iter: int = 200, gt
         pg, pb = m.predict(graphs)
     t_predict = time.perf_counter() - t0
     rows = []
-    t_plain = t_learned = 0.0
+    t_plain = t_learned = t_plain_target = t_learned_target = 0.0
     for i, g in enumerate(graphs):
         with QaoaHandle.maxcut(g.n, g.edges, g.weights) as h:
             cmax = h.cost_extrema()[1]
-            t0 = time.perf_counter()
-            _, E_plain, tr_plain = _lbfgs_counted(h, x_ramp, p, max_iter, gtol)
-            t_plain += time.perf_counter() - t0
+            E_plain, tr_plain, tm_plain = _lbfgs_counted(h, x_ramp, p, max_iter, gtol)
+            r_plain = E_plain / cmax
+            target = (r_plain - tol) * cmax
             t0 = time.perf_counter()
             x_learn = np.concatenate([pg[i], pb[i]])
             E_l0 = h.evaluate(pg[i], pb[i])
             E_r0 = h.evaluate(g_ramp[0], b_ramp[0])
+            t_starts = time.perf_counter() - t0
             start = x_learn if E_l0 >= E_r0 else x_ramp
-            _, E_learn, tr_learn = _lbfgs_counted(h, start, p, max_iter, gtol)
-            t_learned += time.perf_counter() - t0
-        r_plain, r_learn = E_plain / cmax, E_learn / cmax
-        target = (r_plain - tol) * cmax
+            if max(E_l0, E_r0) >= target:
+                E_learn, tr_learn, tm_learn = max(E_l0, E_r0), np.zeros(0), np.zeros(0)
+                if not learned_until_target:
+                    E_learn, tr_learn, tm_learn = _lbfgs_counted(h, start, p, max_iter, gtol)
+            else:
+                E_learn, tr_learn, tm_learn = _lbfgs_counted(
+                    h, start, p, max_iter, gtol, stop_at=target if learned_until_target else None)
+        t_plain += float(tm_plain[-1])
+        t_learned += t_starts + (float(tm_learn[-1]) if tm_learn.size else 0.0)
+        r_learn = E_learn / cmax
         n_plain = evals_to_reach(tr_plain, target)
         n_learn = evals_to_reach(np.concatenate([[max(E_l0, E_r0)], tr_learn]), target)
+        t_plain_target += float(tm_plain[n_plain - 1])
+        if n_learn is None:
+            t_learned_target += t_starts + float(tm_learn[-1])
+        else:
+            t_learned_target += t_starts + (float(tm_learn[n_learn - 2]) if n_learn >= 2 else 0.0)
         rows.append(dict(n=g.n, cmax=cmax, r_plain=r_plain, r_learned=r_learn, r_start_learned=E_l0 / cmax,
                          r_start_ramp=E_r0 / cmax, evals_plain=len(tr_plain), evals_plain_to_target=n_plain,
                          evals_learned_to_target=(None if n_learn is None else n_learn + 1),
                          evals_learned=len(tr_learn) + 2, used_learned_start=bool(E_l0 >= E_r0)))
         if log and (i % 32 == 0 or i == len(graphs) - 1):
             log(f"[warmstart] eval {i + 1}/{len(graphs)}: r_plain {r_plain:.4f} r_learned {r_learn:.4f}")
+
     def tot(k, full=None):
         # a run that never reaches the target is charged all of its evaluations
         return int(sum(r[k] if r[k] is not None else r[full] for r in rows if r[k] is not None or full))
     reached = [r for r in rows if r["evals_learned_to_target"] is not None]
     return {
-        "graphs": len(rows), "p": p, "tolerance": tol,
+        "graphs": len(rows), "p": p, "tolerance": tol, "learned_until_target": learned_until_target,
         "mean_ratio_plain": float(np.mean([r["r_plain"] for r in rows])),
         "mean_ratio_learned": float(np.mean([r["r_learned"] for r in rows])),
         "mean_start_ratio_ramp": float(np.mean([r["r_start_ramp"] for r in rows])),
@@ -176,6 +208,7 @@ def evaluate(params, graphs, p: int, tol: float = 0.005, max_iter: int = 200, gt
         "total_evals_learned_to_target": tot("evals_learned_to_target", "evals_learned"),
         "learned_reached_target": len(reached),
         "seconds_plain": t_plain, "seconds_learned": t_learned + t_predict, "seconds_predict": t_predict,
+        "seconds_plain_to_target": t_plain_target, "seconds_learned_to_target": t_learned_target + t_predict,
         "rows": rows,
     }
 
