@@ -53,6 +53,7 @@ struct qaoa_handle_s {
     size_t parts_cap = 0;  // doubles
     double *res = nullptr;
     size_t res_cap = 0;    // doubles
+    std::vector<qk::PassPlan> plan;  // mixer sweeps of one layer (fixed by n and precision)
     bool state_valid = false;
     bool poisoned = false;
     bool extrema_valid = false;
@@ -346,7 +347,7 @@ qaoa_status drain_profile(qaoa_handle h)
 qaoa_status run_forward(qaoa_handle h, int p, const double *gamma, const double *beta,
                         bool skip_last, bool e_out)
 {
-    const std::vector<qk::PassPlan> G = qk::plan_passes(h->n, c64(h));
+    const std::vector<qk::PassPlan> &G = h->plan;
     const int P = (int)G.size();
     for (int l = 0; l < p; ++l) {
         for (int idx = 0; idx < P; ++idx) {
@@ -380,6 +381,78 @@ qaoa_status run_forward(qaoa_handle h, int p, const double *gamma, const double 
     return QAOA_OK;
 }
 
+// Launch sequence of the expectation and its adjoint gradient (Sec. II-B,
+// IV-C) on the handle's stream: forward sweeps, the turn sweep, backward
+// sweeps.  `lam` is the adjoint vector (2^n amplitudes) and `parts` holds
+// (2p + 1) x nblocks partial sums: slot 0 E, slots 1 .. p the <lam|X|phi>
+// terms of layers 0 .. p-1, slots p+1 .. 2p their <lam|C|phi> terms.  Every
+// slot is overwritten before it is added to, so neither buffer needs clearing.
+// Only enqueues kernels (p >= 1); allocates nothing.
+qaoa_status enqueue_gradient(qaoa_handle h, int p, const double *gamma, const double *beta, void *lam,
+                             double *parts)
+{
+    qaoa_status st;
+    const uint64_t T = nblocks(h);
+    const std::vector<qk::PassPlan> &G = h->plan;
+    const int P = (int)G.size();
+    double *slotE = parts;
+    auto slotB = [&](int l) { return parts + (uint64_t)(1 + l) * T; };
+    auto slotG = [&](int l) { return parts + (uint64_t)(1 + p + l) * T; };
+
+    // Forward through every group except the last group of the last layer.
+    if ((st = run_forward(h, p, gamma, beta, true, false)) != QAOA_OK) return st;
+
+    // Turn pass: last group of layer p-1 forward, E, lam = C phi, group undone on lam.
+    {
+        const int l = p - 1;
+        qk::PassArgs a = pass_args(h, G[P > 1 ? group_at(l, P - 1, P) : 0], beta[l]);
+        a.lam = lam;
+        a.part_e = slotE;
+        a.part_b = slotB(l);
+        if (P == 1) {
+            a.flags |= qk::kPhaseIn | qk::kPhaseOut;
+            a.gamma_in = a.gamma_out = gamma[l];
+            a.part_g = slotG(l);
+            if (l == 0) a.flags |= qk::kInit | qk::kNoStore;
+        }
+        if ((st = run_pass(h, P == 1 ? qk::kTurnPhase : qk::kTurn, a)) != QAOA_OK) return st;
+    }
+    // Backward sweep: each layer undoes its groups in the reverse of the forward
+    // order; a layer's first group also undoes its phase and, for P >= 2 and
+    // l > 0, shares its sweep with the last group of layer l - 1.  Partials of
+    // <lam|X|phi>: with P >= 2 a layer's slot has already been written when its
+    // own passes run (by the turn pass for layer p-1, by the layer-boundary
+    // sweep of layer l+1 otherwise), so they add to it, and a layer-boundary
+    // sweep is always the first to touch layer l-1's slot, so it overwrites it;
+    // with P = 1 every layer but the last has one pass, which overwrites.
+    for (int l = p - 1; l >= 0; --l) {
+        for (int j = 0; j < P; ++j) {
+            const int idx = P - 1 - j;
+            if (j == 0 && (l == p - 1 || P > 1)) continue;  // turn pass, or fused into layer l+1
+            const int gi = P > 1 ? group_at(l, idx, P) : 0;
+            qk::PassArgs a = pass_args(h, G[gi], beta[l]);
+            a.lam = lam;
+            a.part_b = slotB(l);
+            if (P > 1) a.flags |= qk::kBetaAcc;
+            int mode = qk::kBwd;
+            if (idx == 0) {
+                a.gamma_out = gamma[l];
+                a.part_g = slotG(l);
+                if (P > 1 && l > 0) {
+                    mode = qk::kBwdFuse;
+                    set_second(a, beta[l - 1]);
+                    a.part_b2 = slotB(l - 1);
+                } else {
+                    a.flags |= qk::kPhaseOut;
+                    if (l == 0) a.flags |= qk::kNoStore;
+                }
+            }
+            if ((st = run_pass(h, mode, a)) != QAOA_OK) return st;
+        }
+    }
+    return QAOA_OK;
+}
+
 qaoa_status fetch_results(qaoa_handle h, int nslots, uint64_t count, double *host)
 {
     HIPCHECK(h, qk::launch_sum_slots(h->parts, count, count, nslots, h->res, h->stream));
@@ -401,6 +474,12 @@ qaoa_status create_common(int32_t n, int32_t precision, void *stream, qaoa_handl
     h->prec = precision;
     h->N = 1ull << n;
     h->alloc = g_alloc;
+    try {
+        h->plan = qk::plan_passes(n, precision == QAOA_C64);
+    } catch (...) {
+        delete h;
+        return fail(QAOA_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) {
         delete h;
@@ -448,36 +527,61 @@ qaoa_status create_common(int32_t n, int32_t precision, void *stream, qaoa_handl
     return QAOA_OK;
 }
 
-// Copies host term arrays to the device (through the handle's allocator),
-// builds the cost diagonal, frees the copies once the stream has drained.
-template <typename Launch>
-qaoa_status build_cost(qaoa_handle h, const std::vector<std::pair<const void *, size_t>> &arrays,
-                       Launch launch)
+// Uploads the cost pieces (through the handle's allocator), builds the cost
+// diagonal, frees the upload once the stream has drained.
+qaoa_status build_cost(qaoa_handle h, const std::vector<qk::CostPiece> &pieces, double offset)
 {
-    std::vector<void *> dev(arrays.size(), nullptr);
+    const size_t bytes = pieces.size() * sizeof(qk::CostPiece);
+    void *dev = nullptr;
+    if (bytes) {
+        hipError_t e = dev_alloc(h, &dev, bytes);
+        if (e == hipErrorOutOfMemory || (e == hipSuccess && !dev))
+            return fail(QAOA_ERR_OUT_OF_MEMORY, "term upload buffer allocation failed");
+        if (e != hipSuccess) return device_fail(h, "term upload allocation", e);
+    }
     qaoa_status st = QAOA_OK;
-    for (size_t i = 0; i < arrays.size() && st == QAOA_OK; ++i) {
-        if (!arrays[i].first || arrays[i].second == 0) continue;
-        hipError_t e = dev_alloc(h, &dev[i], arrays[i].second);
-        if (e == hipErrorOutOfMemory) {
-            dev[i] = nullptr;
-            st = fail(QAOA_ERR_OUT_OF_MEMORY, "term upload buffer allocation failed");
-            break;
-        }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(dev[i], arrays[i].first, arrays[i].second, hipMemcpyHostToDevice,
-                               h->stream);
-        if (e != hipSuccess) st = device_fail(h, "term upload", e);
+    hipError_t e = hipSuccess;
+    if (bytes) e = hipMemcpyAsync(dev, pieces.data(), bytes, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = qk::launch_cost_pieces(c64(h), h->cost, h->n, (const qk::CostPiece *)dev,
+                                   (int64_t)pieces.size(), offset, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        st = device_fail(h, "cost diagonal", e);
+        (void)hipStreamSynchronize(h->stream);  // queued work must finish before the free
     }
-    if (st == QAOA_OK) {
-        hipError_t e = launch(dev);
-        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-        if (e != hipSuccess) st = device_fail(h, "cost diagonal", e);
-    } else {
-        (void)hipStreamSynchronize(h->stream);  // copies already queued must finish before the frees
-    }
-    for (size_t i = 0; i < dev.size(); ++i) dev_free(h, dev[i], arrays[i].second);
+    dev_free(h, dev, bytes);
     return st;
+}
+
+// Builds the pieces of a cost (host vectors; a failed allocation is reported).
+template <typename Make>
+qaoa_status make_pieces(std::vector<qk::CostPiece> *out, Make make)
+{
+    try {
+        *out = make();
+    } catch (...) {
+        return fail(QAOA_ERR_OUT_OF_MEMORY, "host allocation of the cost terms failed");
+    }
+    return QAOA_OK;
+}
+
+// Creates the handle and its cost diagonal from pieces; on error nothing is left.
+qaoa_status create_with_pieces(int32_t n, int32_t precision, void *stream, qaoa_handle *out,
+                               const std::vector<qk::CostPiece> &pieces, double offset)
+{
+    qaoa_handle h = nullptr;
+    qaoa_status st = create_common(n, precision, stream, out, &h);
+    if (st != QAOA_OK) return st;
+    st = build_cost(h, pieces, offset);
+    if (st != QAOA_OK) {
+        std::string keep = g_err;
+        qaoa_destroy(h);
+        g_err = keep;
+        return st;
+    }
+    *out = h;
+    return QAOA_OK;
 }
 
 }  // namespace
@@ -489,21 +593,11 @@ qaoa_status qaoa_create_maxcut(int32_t n, int64_t m, const int32_t *edges, const
 {
     qaoa_status st = check_terms(n, m, edges, w, false);
     if (st != QAOA_OK) return st;
-    qaoa_handle h = nullptr;
-    if ((st = create_common(n, precision, stream, out, &h)) != QAOA_OK) return st;
-    st = build_cost(h, {{edges, (size_t)m * 2 * sizeof(int32_t)}, {w, w ? (size_t)m * sizeof(double) : 0}},
-                    [&](std::vector<void *> &d) {
-                        return qk::launch_cost_maxcut(c64(h), h->cost, n, m, (const int32_t *)d[0],
-                                                      (const double *)d[1], h->stream);
-                    });
-    if (st != QAOA_OK) {
-        std::string keep = g_err;
-        qaoa_destroy(h);
-        g_err = keep;
+    if (!out) return fail(QAOA_ERR_INVALID_ARGUMENT, "out is NULL");
+    std::vector<qk::CostPiece> pieces;
+    if ((st = make_pieces(&pieces, [&] { return qk::cost_pieces_maxcut(m, edges, w); })) != QAOA_OK)
         return st;
-    }
-    *out = h;
-    return QAOA_OK;
+    return create_with_pieces(n, precision, stream, out, pieces, 0.0);
 }
 
 qaoa_status qaoa_create_qubo(int32_t n, int64_t m, const int32_t *pairs, const double *J,
@@ -516,25 +610,11 @@ qaoa_status qaoa_create_qubo(int32_t n, int64_t m, const int32_t *pairs, const d
     if (hl)
         for (int i = 0; i < n; ++i)
             if (!std::isfinite(hl[i])) return fail(QAOA_ERR_INVALID_ARGUMENT, "h must be finite");
-    qaoa_handle h = nullptr;
-    if ((st = create_common(n, precision, stream, out, &h)) != QAOA_OK) return st;
-    st = build_cost(h,
-                    {{pairs, (size_t)m * 2 * sizeof(int32_t)},
-                     {J, (size_t)m * sizeof(double)},
-                     {hl, hl ? (size_t)n * sizeof(double) : 0}},
-                    [&](std::vector<void *> &d) {
-                        return qk::launch_cost_qubo(c64(h), h->cost, n, m, (const int32_t *)d[0],
-                                                    (const double *)d[1], (const double *)d[2],
-                                                    offset, h->stream);
-                    });
-    if (st != QAOA_OK) {
-        std::string keep = g_err;
-        qaoa_destroy(h);
-        g_err = keep;
+    if (!out) return fail(QAOA_ERR_INVALID_ARGUMENT, "out is NULL");
+    std::vector<qk::CostPiece> pieces;
+    if ((st = make_pieces(&pieces, [&] { return qk::cost_pieces_qubo(n, m, pairs, J, hl); })) != QAOA_OK)
         return st;
-    }
-    *out = h;
-    return QAOA_OK;
+    return create_with_pieces(n, precision, stream, out, pieces, offset);
 }
 
 qaoa_status qaoa_create_poly(int32_t n, int64_t L, const uint64_t *masks, const double *w,
@@ -553,22 +633,11 @@ qaoa_status qaoa_create_poly(int32_t n, int64_t L, const uint64_t *masks, const 
         }
         if (!std::isfinite(w[k])) return fail(QAOA_ERR_INVALID_ARGUMENT, "weights must be finite");
     }
-    qaoa_handle h = nullptr;
-    qaoa_status st = create_common(n, precision, stream, out, &h);
+    if (!out) return fail(QAOA_ERR_INVALID_ARGUMENT, "out is NULL");
+    std::vector<qk::CostPiece> pieces;
+    qaoa_status st = make_pieces(&pieces, [&] { return qk::cost_pieces_poly(L, masks, w); });
     if (st != QAOA_OK) return st;
-    st = build_cost(h, {{masks, (size_t)L * sizeof(uint64_t)}, {w, (size_t)L * sizeof(double)}},
-                    [&](std::vector<void *> &d) {
-                        return qk::launch_cost_poly(c64(h), h->cost, n, L, (const uint64_t *)d[0],
-                                                    (const double *)d[1], offset, h->stream);
-                    });
-    if (st != QAOA_OK) {
-        std::string keep = g_err;
-        qaoa_destroy(h);
-        g_err = keep;
-        return st;
-    }
-    *out = h;
-    return QAOA_OK;
+    return create_with_pieces(n, precision, stream, out, pieces, offset);
 }
 
 qaoa_status qaoa_destroy(qaoa_handle h)
@@ -736,63 +805,7 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
     if ((st = ensure_doubles(h, &h->res, &h->res_cap, (size_t)nslots)) != QAOA_OK) return st;
     h->state_valid = false;
 
-    const std::vector<qk::PassPlan> G = qk::plan_passes(h->n, c64(h));
-    const int P = (int)G.size();
-    double *slotE = h->parts;
-    auto slotB = [&](int l) { return h->parts + (uint64_t)(1 + l) * T; };
-    auto slotG = [&](int l) { return h->parts + (uint64_t)(1 + p + l) * T; };
-
-    // Forward through every group except the last group of the last layer.
-    if ((st = run_forward(h, p, gamma, beta, true, false)) != QAOA_OK) return st;
-
-    // Turn pass: last group of layer p-1 forward, E, lam = C phi, group undone on lam.
-    {
-        const int l = p - 1;
-        qk::PassArgs a = pass_args(h, G[P > 1 ? group_at(l, P - 1, P) : 0], beta[l]);
-        a.part_e = slotE;
-        a.part_b = slotB(l);
-        if (P == 1) {
-            a.flags |= qk::kPhaseIn | qk::kPhaseOut;
-            a.gamma_in = a.gamma_out = gamma[l];
-            a.part_g = slotG(l);
-            if (l == 0) a.flags |= qk::kInit | qk::kNoStore;
-        }
-        if ((st = run_pass(h, P == 1 ? qk::kTurnPhase : qk::kTurn, a)) != QAOA_OK) return st;
-    }
-    // Backward sweep: each layer undoes its groups in the reverse of the forward
-    // order; a layer's first group also undoes its phase and, for P >= 2 and
-    // l > 0, shares its sweep with the last group of layer l - 1.  The first
-    // pass to touch a layer's <lam|X|phi> partials overwrites them, later
-    // passes add to them (the turn pass wrote layer p-1's).
-    std::vector<char> written((size_t)p, 0);
-    written[p - 1] = 1;
-    for (int l = p - 1; l >= 0; --l) {
-        for (int j = 0; j < P; ++j) {
-            const int idx = P - 1 - j;
-            if (j == 0 && (l == p - 1 || P > 1)) continue;  // turn pass, or fused into layer l+1
-            const int gi = P > 1 ? group_at(l, idx, P) : 0;
-            qk::PassArgs a = pass_args(h, G[gi], beta[l]);
-            a.part_b = slotB(l);
-            if (written[l]) a.flags |= qk::kBetaAcc;
-            written[l] = 1;
-            int mode = qk::kBwd;
-            if (idx == 0) {
-                a.gamma_out = gamma[l];
-                a.part_g = slotG(l);
-                if (P > 1 && l > 0) {
-                    mode = qk::kBwdFuse;
-                    set_second(a, beta[l - 1]);
-                    a.part_b2 = slotB(l - 1);
-                    if (written[l - 1]) a.flags |= qk::kBetaAcc2;
-                    written[l - 1] = 1;
-                } else {
-                    a.flags |= qk::kPhaseOut;
-                    if (l == 0) a.flags |= qk::kNoStore;
-                }
-            }
-            if ((st = run_pass(h, mode, a)) != QAOA_OK) return st;
-        }
-    }
+    if ((st = enqueue_gradient(h, p, gamma, beta, h->lam, h->parts)) != QAOA_OK) return st;
     std::vector<double> r((size_t)nslots);
     if ((st = fetch_results(h, nslots, T, r.data())) != QAOA_OK) return st;
     if (E) *E = r[0];

@@ -182,33 +182,16 @@ __global__ __launch_bounds__(kThreads) void k_minmax_final(const double *pmin, c
 // A workgroup builds 4096 consecutive entries of the cost diagonal per
 // iteration.  Thread (lane, wave) holds the 16 entries z = base | q << 6 |
 // lane | wave << 10, q < 16, so every store of a wave is 64 consecutive
-// entries.  Each term is then added to all 16 entries by one fp64 FMA each,
-// acc += a w with a in {0, 1}: the same rounding as adding w when the term is
-// active and no change otherwise, so every entry is summed in the given term
-// order exactly as term-by-term addition would.  Whether the term is active is
-// a 16-bit mask over q: for a variable outside bits 6-9 it is all ones or all
-// zeros for the thread, for variable 6 + b it is the set of q with bit b.
+// entries, and z bits >= 10 are the same for the whole wavefront.  The terms
+// arrive as pieces (cost_terms.cpp): a piece whose wave-bit literals fail is
+// skipped by the whole wavefront with a scalar branch, lanes that fail its
+// lane-bit literals sit it out under the execution mask, and the rest add to
+// entry q the piece's wq[q]: its weight where the piece covers q, -0.0 where
+// it does not (x + (-0.0) == x exactly in round-to-nearest, signed zeros
+// included).  Each entry thus receives exactly the weights of its active
+// terms, added one by one in the given term order, as the definition sums
+// them.
 constexpr int kCostTileBits = 12;
-
-__device__ __forceinline__ uint32_t var_mask(uint64_t zt, int v)
-{
-    if (v >= 6 && v < 10) return v == 6 ? 0xAAAAu : v == 7 ? 0xCCCCu : v == 8 ? 0xF0F0u : 0xFF00u;
-    return ((zt >> v) & 1ull) ? 0xFFFFu : 0u;
-}
-__device__ __forceinline__ bool in_reg_bits(int v) { return v >= 6 && v < 10; }
-
-// acc[q] += w for each q whose bit is set in mk; `uniform` when mk is 0 or 0xFFFF.
-__device__ __forceinline__ void add_term(double (&acc)[16], uint32_t mk, double w, bool uniform)
-{
-    if (uniform) {
-        const double a = (double)(mk & 1u);
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = fma(a, w, acc[q]);
-    } else {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = fma((double)((mk >> q) & 1u), w, acc[q]);
-    }
-}
 
 template <typename CT>
 __device__ __forceinline__ void store_costs(CT *__restrict__ C, uint64_t N, uint64_t zt, const double (&acc)[16])
@@ -220,76 +203,32 @@ __device__ __forceinline__ void store_costs(CT *__restrict__ C, uint64_t N, uint
     }
 }
 
-__device__ __forceinline__ uint64_t cost_thread_base(uint64_t tile)
-{
-    return (tile << kCostTileBits) | ((uint64_t)(threadIdx.x >> 6) << 10) | (threadIdx.x & 63u);
-}
-
-// C[z] = sum over cut edges of w_k, in edge order (Sec. IV-A; MaxCut term = x_i XOR x_j).
 template <typename CT>
-__global__ __launch_bounds__(kThreads) void k_cost_maxcut(CT *__restrict__ C, uint64_t N, int64_t m,
-                                                          const int32_t *__restrict__ edges,
-                                                          const double *__restrict__ w)
+__global__ __launch_bounds__(kThreads) void k_cost_pieces(CT *__restrict__ C, uint64_t N,
+                                                          const CostPiece *__restrict__ P,
+                                                          int64_t count, double offset)
 {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (uint64_t tile = blockIdx.x; (tile << kCostTileBits) < N; tile += gridDim.x) {
-        const uint64_t zt = cost_thread_base(tile);
-        double acc[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-        for (int64_t k = 0; k < m; ++k) {
-            const int i = edges[2 * k], j = edges[2 * k + 1];
-            const double wk = w ? w[k] : 1.0;
-            add_term(acc, var_mask(zt, i) ^ var_mask(zt, j), wk, !in_reg_bits(i) && !in_reg_bits(j));
-        }
-        store_costs(C, N, zt, acc);
-    }
-}
-
-// C[z] = offset + sum_k J_k x_i x_j + sum_i h_i x_i in that order (Eq. (2), degree <= 2).
-template <typename CT>
-__global__ __launch_bounds__(kThreads) void k_cost_qubo(CT *__restrict__ C, uint64_t N, int n, int64_t m,
-                                                        const int32_t *__restrict__ pairs,
-                                                        const double *__restrict__ J,
-                                                        const double *__restrict__ h, double offset)
-{
-    for (uint64_t tile = blockIdx.x; (tile << kCostTileBits) < N; tile += gridDim.x) {
-        const uint64_t zt = cost_thread_base(tile);
+        const uint64_t zw = (tile << kCostTileBits) | ((uint64_t)wave << 10);
         double acc[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) acc[q] = offset;
-        for (int64_t k = 0; k < m; ++k) {
-            const int i = pairs[2 * k], j = pairs[2 * k + 1];
-            add_term(acc, var_mask(zt, i) & var_mask(zt, j), J[k], !in_reg_bits(i) && !in_reg_bits(j));
-        }
-        if (h)
-            for (int i = 0; i < n; ++i) add_term(acc, var_mask(zt, i), h[i], !in_reg_bits(i));
-        store_costs(C, N, zt, acc);
-    }
-}
-
-// General 0-1 polynomial of Eq. (2): term k (mask m_k, weight w_k) is active in
-// z iff every variable of its mask is 1, (z AND m_k) == m_k; terms are added in
-// the given order after the offset.
-template <typename CT>
-__global__ __launch_bounds__(kThreads) void k_cost_poly(CT *__restrict__ C, uint64_t N, int64_t L,
-                                                        const uint64_t *__restrict__ masks,
-                                                        const double *__restrict__ w, double offset)
-{
-    constexpr uint64_t kRegBits = 0xFull << 6;
-    for (uint64_t tile = blockIdx.x; (tile << kCostTileBits) < N; tile += gridDim.x) {
-        const uint64_t zt = cost_thread_base(tile);
-        double acc[16];
+        for (int64_t k = 0; k < count; ++k) {
+            const CostPiece &pc = P[k];
+            const uint64_t um = pc.umask, uv = pc.uval;
+            const uint32_t ln = pc.lanes;
+            if ((zw & um) != uv) continue;  // the whole wavefront skips the piece
+            double wq[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = offset;
-        for (int64_t k = 0; k < L; ++k) {
-            const uint64_t mk = masks[k], out = mk & ~kRegBits;
-            uint32_t qm = 0xFFFFu;  // q whose register-held variables are all 1
+            for (int q = 0; q < 16; ++q) wq[q] = pc.wq[q];
+            if ((lane & ln & 63u) == (ln >> 8)) {  // lanes failing the test sit it out
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if ((mk >> (6 + b)) & 1ull) qm &= var_mask(0, 6 + b);
-            add_term(acc, ((zt & out) == out) ? qm : 0u, w[k], (mk & kRegBits) == 0);
+                for (int q = 0; q < 16; ++q) acc[q] += wq[q];
+            }
         }
-        store_costs(C, N, zt, acc);
+        store_costs(C, N, zw | lane, acc);
     }
 }
 
@@ -552,42 +491,16 @@ hipError_t launch_sum_slots(const double *parts, uint64_t count, uint64_t stride
     return hipGetLastError();
 }
 
-hipError_t launch_cost_maxcut(bool c64, void *C, int n, int64_t m, const int32_t *edges,
-                              const double *w, hipStream_t s)
+hipError_t launch_cost_pieces(bool c64, void *C, int n, const CostPiece *pieces, int64_t count,
+                              double offset, hipStream_t s)
 {
     const uint64_t N = 1ull << n;
     if (c64)
-        hipLaunchKernelGGL(k_cost_maxcut<float>, dim3(cost_grid(N)), dim3(kThreads), 0, s,
-                           (float *)C, N, m, edges, w);
+        hipLaunchKernelGGL(k_cost_pieces<float>, dim3(cost_grid(N)), dim3(kThreads), 0, s,
+                           (float *)C, N, pieces, count, offset);
     else
-        hipLaunchKernelGGL(k_cost_maxcut<double>, dim3(cost_grid(N)), dim3(kThreads), 0, s,
-                           (double *)C, N, m, edges, w);
-    return hipGetLastError();
-}
-
-hipError_t launch_cost_qubo(bool c64, void *C, int n, int64_t m, const int32_t *pairs,
-                            const double *J, const double *h, double offset, hipStream_t s)
-{
-    const uint64_t N = 1ull << n;
-    if (c64)
-        hipLaunchKernelGGL(k_cost_qubo<float>, dim3(cost_grid(N)), dim3(kThreads), 0, s,
-                           (float *)C, N, n, m, pairs, J, h, offset);
-    else
-        hipLaunchKernelGGL(k_cost_qubo<double>, dim3(cost_grid(N)), dim3(kThreads), 0, s,
-                           (double *)C, N, n, m, pairs, J, h, offset);
-    return hipGetLastError();
-}
-
-hipError_t launch_cost_poly(bool c64, void *C, int n, int64_t L, const uint64_t *masks,
-                            const double *w, double offset, hipStream_t s)
-{
-    const uint64_t N = 1ull << n;
-    if (c64)
-        hipLaunchKernelGGL(k_cost_poly<float>, dim3(cost_grid(N)), dim3(kThreads), 0, s,
-                           (float *)C, N, L, masks, w, offset);
-    else
-        hipLaunchKernelGGL(k_cost_poly<double>, dim3(cost_grid(N)), dim3(kThreads), 0, s,
-                           (double *)C, N, L, masks, w, offset);
+        hipLaunchKernelGGL(k_cost_pieces<double>, dim3(cost_grid(N)), dim3(kThreads), 0, s,
+                           (double *)C, N, pieces, count, offset);
     return hipGetLastError();
 }
 

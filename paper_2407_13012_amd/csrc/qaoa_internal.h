@@ -106,12 +106,32 @@ struct PassArgs {
 hipError_t launch_pass(int mode, bool c64, const PassArgs &a, uint64_t nblocks, hipStream_t s);
 hipError_t launch_sum_slots(const double *parts, uint64_t count, uint64_t stride, int nslots,
                             double *out, hipStream_t s);
-hipError_t launch_cost_maxcut(bool c64, void *C, int n, int64_t m, const int32_t *edges,
-                              const double *w, hipStream_t s);
-hipError_t launch_cost_qubo(bool c64, void *C, int n, int64_t m, const int32_t *pairs,
-                            const double *J, const double *h, double offset, hipStream_t s);
-hipError_t launch_cost_poly(bool c64, void *C, int n, int64_t L, const uint64_t *masks,
-                            const double *w, double offset, hipStream_t s);
+
+// Cost diagonal (Sec. IV-A, Eq. (2)).  The kernel gives each thread 16
+// entries: z bits 0-5 are its lane, bits 6-9 the entry index q, and bits >= 10
+// are common to a wavefront.  Terms are uploaded as pieces (cost_terms.cpp):
+// a piece adds w to entry q of a thread when the wave bits match
+// (z & umask) == uval, the lane bits match (lane & lm) == lv, and bit q of
+// qpat is set (wq[q] holds w there and -0.0 elsewhere).  The pieces of one
+// term cover disjoint sets of z.
+constexpr int kCostLaneBits = 6;
+constexpr int kCostUniformBit = 10;
+struct CostPiece {
+    uint64_t umask;  // tested z bits >= 10
+    uint64_t uval;   // their required values
+    uint32_t lanes;  // bits 0-5: tested lane bits lm; bits 8-13: required values lv
+    uint32_t qpat;   // entries q (bit q) covered, from the literals on bits 6-9
+    double w;        // the term's weight
+    double wq[16];   // per entry q: w if bit q of qpat is set, else -0.0
+};
+std::vector<CostPiece> cost_pieces_maxcut(int64_t m, const int32_t *edges, const double *w);
+std::vector<CostPiece> cost_pieces_qubo(int n, int64_t m, const int32_t *pairs, const double *J,
+                                        const double *h);
+std::vector<CostPiece> cost_pieces_poly(int64_t L, const uint64_t *masks, const double *w);
+// C[z] = offset + the weights of the pieces covering z, in piece order;
+// `pieces` is device memory.
+hipError_t launch_cost_pieces(bool c64, void *C, int n, const CostPiece *pieces, int64_t count,
+                              double offset, hipStream_t s);
 hipError_t launch_fill_plus(bool c64, void *psi, int n, hipStream_t s);
 hipError_t launch_expect(bool c64, const void *psi, const void *C, int n, double *parts,
                          hipStream_t s);

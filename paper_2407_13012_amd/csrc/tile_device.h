@@ -138,6 +138,26 @@ __device__ __forceinline__ uint64_t dep(uint32_t e, const Geometry &g)
     return o;
 }
 
+// Offset of register r in arrangement ARR (the part of an amplitude's global
+// index that depends on r only).  dep() sends each tile bit to one global
+// bit, and the register index occupies its own tile bits, so the offset of r
+// is the OR of the offsets of its set bits: four dep() evaluations per
+// arrangement instead of one per register.
+template <int ARR, int WB>
+struct RegOffsets {
+    uint64_t b[4];
+    __device__ __forceinline__ explicit RegOffsets(const Geometry &g)
+    {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[q] = dep(elem<ARR, WB>(0, 0, 1u << q), g);
+    }
+    __device__ __forceinline__ uint64_t operator()(int r) const
+    {
+        return ((r & 1) ? b[0] : 0ull) | ((r & 2) ? b[1] : 0ull) | ((r & 4) ? b[2] : 0ull) |
+               ((r & 8) ? b[3] : 0ull);
+    }
+};
+
 // Tile index -> base index of the tile (the tile bits set to zero).
 __device__ __forceinline__ uint64_t tile_base(uint64_t t, const Geometry &g)
 {
@@ -565,8 +585,10 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
     // part that depends on r only (the same for every thread of the grid).
     const uint64_t thrA = base | dep(elem<0, WB>(lane, wave, 0), g);
     const uint64_t thrC = base | dep(elem<2, WB>(lane, wave, 0), g);
-#define ZA(r) (thrA | dep(elem<0, WB>(0, 0, (r)), g))
-#define ZC(r) (thrC | dep(elem<2, WB>(0, 0, (r)), g))
+    const RegOffsets<0, WB> offA(g);
+    const RegOffsets<2, WB> offC(g);
+#define ZA(r) (thrA | offA(r))
+#define ZC(r) (thrC | offC(r))
 #define VA(r) (full || elem<0, WB>(lane, wave, (r)) < lim)
 #define VC(r) (full || elem<2, WB>(lane, wave, (r)) < lim)
     // Block sums of the tile's E, <lam|X|phi> and <lam|C|phi> terms, taken
@@ -855,15 +877,17 @@ __device__ __forceinline__ void tile_pass_fwd_fuse(const PassArgs &a, uint64_t t
     const CT *cost = (const CT *)a.cost;
     const uint64_t thrA = base | dep(elem<0, WB>(lane, wave, 0), g);
     const uint64_t thrC = base | dep(elem<2, WB>(lane, wave, 0), g);
+    const RegOffsets<0, WB> offA(g);
+    const RegOffsets<2, WB> offC(g);
     const V zero = {(R)0, (R)0};
     CT cv[NR];
     V v[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r)
-        cv[r] = (full || elem<2, WB>(lane, wave, r) < lim) ? ld(&cost[thrC | dep(elem<2, WB>(0, 0, r), g)], strm) : (CT)0;
+        cv[r] = (full || elem<2, WB>(lane, wave, r) < lim) ? ld(&cost[thrC | offC(r)], strm) : (CT)0;
 #pragma unroll
     for (int r = 0; r < NR; ++r)
-        v[r] = (full || elem<0, WB>(lane, wave, r) < lim) ? ld(&psi[thrA | dep(elem<0, WB>(0, 0, r), g)], strm) : zero;
+        v[r] = (full || elem<0, WB>(lane, wave, r) < lim) ? ld(&psi[thrA | offA(r)], strm) : zero;
     const R m1 = (R)a.mul_f, m2 = (R)a.mul_f2;
     mix_stage<0, TM>(v, m1, tmask);
     xpose<0, 1>(v, lds, lane, wave);
@@ -887,7 +911,7 @@ __device__ __forceinline__ void tile_pass_fwd_fuse(const PassArgs &a, uint64_t t
     asm volatile("" : "+v"(thrS));
 #pragma unroll
     for (int r = 0; r < NR; ++r)
-        if (full || elem<0, WB>(lane, wave, r) < lim) st(vscale(v[r], s2), &psi[thrS | dep(elem<0, WB>(0, 0, r), g)], strm);
+        if (full || elem<0, WB>(lane, wave, r) < lim) st(vscale(v[r], s2), &psi[thrS | offA(r)], strm);
 }
 
 }  // namespace

@@ -60,7 +60,11 @@ def test_lbfgs_regular26_iterates_match_oracle(regular26, prec):
     path); the oracle's E and gradient are evaluated at the GPU's own iterates
     0, 20, 40, ..., 200 and at the returned optimum, and compared with the GPU's
     values there: complex128 to 1e-10 sum|w| (E) and 1e-8 (gradient), complex64
-    to 1e-4 relative (E) and 1e-4 |g_k| + 1e-5 max|g| per component."""
+    to 1e-4 relative (E) and, per component, 1e-4 of the gradient's scale: the
+    largest oracle component at that point or at the start of the run,
+    whichever is larger.  (The complex64 error of a component follows the fp32
+    rounding of the amplitudes whose products it sums, not the component's own
+    size, which goes to zero as the run approaches an optimum.)"""
     w, C = regular26
     inst = w["instance"]
     p = len(w["gamma"])
@@ -75,21 +79,26 @@ def test_lbfgs_regular26_iterates_match_oracle(regular26, prec):
     assert it >= 20 and E > tE[0] + 0.1
     assert np.all(np.diff(tE[:it + 1]) >= -1e-9 * wsum)     # maximisation: E never decreases
     worst = {"E": 0.0, "grad": 0.0}
+    gscale0 = None
     for (k, gk, bk, Ek), (Eg, dg, db) in zip(points, gpu):
         E_ref, dg_ref, db_ref = oracle.gradient(inst.n, C, gk, bk)
         gr = np.concatenate([dg_ref, db_ref])
         d = np.abs(np.concatenate([dg, db]) - gr)
+        if gscale0 is None:
+            gscale0 = float(np.abs(gr).max())          # iterate 0: the start of the run
+        gscale = max(float(np.abs(gr).max()), gscale0)
         if prec == "c128":
             assert abs(Ek - E_ref) <= 1e-10 * wsum and abs(Eg - E_ref) <= 1e-10 * wsum, (k, Ek, Eg, E_ref)
             assert d.max() <= 1e-8, (k, d.max())
         else:
-            gmax = float(np.abs(gr).max())
             assert abs(Ek - E_ref) <= 1e-4 * abs(E_ref) and abs(Eg - E_ref) <= 1e-4 * abs(E_ref), (k, Ek, E_ref)
-            assert np.all(d <= 1e-4 * np.abs(gr) + 1e-5 * gmax), (k, d, gr)
+            assert d.max() <= 1e-4 * gscale, (k, d, gr, gscale)
         worst["E"] = max(worst["E"], abs(Eg - E_ref) / abs(E_ref))
-        worst["grad"] = max(worst["grad"], float(d.max() / np.abs(gr).max()))
+        worst["grad"] = max(worst["grad"], float(d.max()) / gscale)
+        print(f"{prec}: iterate {k}: |dE|/E {abs(Eg - E_ref) / abs(E_ref):.2e}, max|dg| {d.max():.2e}, "
+              f"max|g| {np.abs(gr).max():.3e}", flush=True)
     print(f"{prec}: pinned iterates {pins} + optimum; worst relative error E {worst['E']:.2e}, "
-          f"gradient {worst['grad']:.2e}", flush=True)
+          f"gradient (to its scale) {worst['grad']:.2e}", flush=True)
     RUNS[prec] = (E, C.max())
 
 
