@@ -167,6 +167,31 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
                           double *E, double *dgamma, double *dbeta);
 
 /*
+ * qaoa_gradient without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same results as qaoa_gradient (the same kernels in the
+ * same order).  The adjoint vector, the partial sums and the summed slots are
+ * taken from a fixed scratch array of 16 MiB + 256 KiB that the library holds
+ * on each device it runs on until the process ends; the handle's state and
+ * cost diagonal (allocated at creation) are used as by qaoa_gradient.
+ *   p                    0 <= p <= 32
+ *   E, dgamma, dbeta     as qaoa_gradient (E may be NULL); host memory, or
+ *                        device memory when out_is_device is nonzero (then
+ *                        nothing is synchronised and the call can be captured
+ *                        into a HIP graph)
+ * Limits: the adjoint vector must fit the scratch: complex128 n <= 20,
+ * complex64 n <= 21; larger n or p gives INVALID_ARGUMENT with the sizes in
+ * the message.  Every call on one device shares that device's scratch, so
+ * calls that overlap on one GPU (other threads, other streams) race; calls
+ * ordered on one stream are safe.  Nothing in the scratch needs clearing:
+ * every slot is written before it is read.  Consumes the state like
+ * qaoa_gradient.  Errors: INVALID_ARGUMENT, DEVICE, UNSUPPORTED (device index
+ * >= 64).
+ */
+qaoa_status qaoa_gradient_noalloc(qaoa_handle h, int32_t p, const double *gamma, const double *beta,
+                                  double *E, double *dgamma, double *dbeta, int32_t out_is_device);
+
+/*
  * Draw `shots` basis states from |psi_z|^2 of the current state and return
  * each with its objective value (Sec. IV-D).  Shot s uses the uniform
  * u_s = top 53 bits of Philox-4x32-10(counter = (s, 0), key = seed) * 2^-53 and

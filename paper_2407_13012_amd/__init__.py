@@ -38,6 +38,7 @@ from ._binding import (  # noqa: F401
     load_library,
     qaoa_cost_diagonal,
     qaoa_cost_extrema,
+    qaoa_gradient_noalloc,
     qaoa_create_maxcut,
     qaoa_create_poly,
     qaoa_create_qubo,

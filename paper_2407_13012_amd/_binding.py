@@ -91,6 +91,7 @@ def load_library() -> ctypes.CDLL:
         "qaoa_expectation": [vp, pd],
         "qaoa_evaluate": [vp, i32, vp, vp, pd],
         "qaoa_gradient": [vp, i32, vp, vp, pd, vp, vp],
+        "qaoa_gradient_noalloc": [vp, i32, vp, vp, vp, vp, vp, i32],
         "qaoa_sample": [vp, i64, u64, vp, vp, i32],
         "qaoa_pass_plan": [i32, i32, i32, pi32, vp, vp],
         "qaoa_lbfgs_minimize": [i32, vp, OBJECTIVE_FN, vp, ctypes.POINTER(LbfgsOptions), pd,
@@ -272,6 +273,34 @@ def qaoa_gradient(h, gamma, beta):
     _check(load_library().qaoa_gradient(h, g.size, _ptr(g), _ptr(b), ctypes.byref(E), _ptr(dg), _ptr(db)),
            "qaoa_gradient")
     return E.value, dg, db
+
+
+def qaoa_gradient_noalloc(h, gamma, beta, out=None):
+    """qaoa_gradient through the library's fixed scratch (no device allocation).
+    Without `out`: returns (E, dE/dgamma, dE/dbeta) on the host.  With `out`, a
+    float64 device tensor of 2p + 1 entries: fills it with (E, dE/dgamma,
+    dE/dbeta) in stream order and returns it."""
+    g, b = _angles(gamma, beta)
+    p = g.size
+    lib = load_library()
+    if out is None:
+        E = ctypes.c_double()
+        dg = np.zeros(p)
+        db = np.zeros(p)
+        _check(lib.qaoa_gradient_noalloc(h, p, _ptr(g), _ptr(b), ctypes.byref(E), _ptr(dg), _ptr(db), 0),
+               "qaoa_gradient_noalloc")
+        return E.value, dg, db
+    if out.numel() != 2 * p + 1 or not out.is_cuda or out.dtype != _torch_float64() or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 device tensor of 2p + 1 entries")
+    base = out.data_ptr()
+    _check(lib.qaoa_gradient_noalloc(h, p, _ptr(g), _ptr(b), ctypes.c_void_p(base), ctypes.c_void_p(base + 8),
+                                     ctypes.c_void_p(base + 8 * (1 + p)), 1), "qaoa_gradient_noalloc")
+    return out
+
+
+def _torch_float64():
+    import torch
+    return torch.float64
 
 
 def qaoa_sample(h, shots: int, seed: int, z_out=None, cost_out=None, with_cost: bool = True):
@@ -622,6 +651,9 @@ class QaoaHandle:
 
     def gradient(self, gamma, beta):
         return qaoa_gradient(self._h, gamma, beta)
+
+    def gradient_noalloc(self, gamma, beta, out=None):
+        return qaoa_gradient_noalloc(self._h, gamma, beta, out)
 
     def sample(self, shots: int, seed: int, **kw):
         return qaoa_sample(self._h, shots, seed, **kw)

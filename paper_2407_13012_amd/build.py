@@ -13,7 +13,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libqaoa.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "batch.hip", "mpnn.hip", "api.cpp", "plan.cpp", "lbfgs.cpp", "cost_terms.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "batch.hip", "mpnn.hip", "api.cpp", "plan.cpp", "lbfgs.cpp", "cost_terms.cpp", "noalloc.hip")]
 ARCH = os.environ.get("QAOA_OFFLOAD_ARCH", "gfx950")
 
 

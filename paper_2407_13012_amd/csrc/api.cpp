@@ -586,6 +586,90 @@ qaoa_status create_with_pieces(int32_t n, int32_t precision, void *stream, qaoa_
 
 }  // namespace
 
+namespace qk {
+
+int handle_device(qaoa_handle h) { return h->device; }
+
+size_t noalloc_need(qaoa_handle h, int p)
+{
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    if (p == 0) return al((size_t)((h->N + kTile - 1) / kTile) * sizeof(double)) + sizeof(double);
+    const size_t nslots = 2 * (size_t)p + 1;
+    return al(h->N * amp_bytes(h->prec)) + al(nslots * nblocks(h) * sizeof(double)) + nslots * sizeof(double);
+}
+
+qaoa_status noalloc_check(qaoa_handle h, int32_t p, const double *gamma, const double *beta,
+                          const double *dgamma, const double *dbeta, size_t cap)
+{
+    qaoa_status st = check_handle(h);
+    if (st != QAOA_OK) return st;
+    if ((st = check_angles(p, gamma, beta)) != QAOA_OK) return st;
+    if (p > kNoAllocMaxLayers) return fail(QAOA_ERR_INVALID_ARGUMENT, "p exceeds the no-allocation limit of 32 layers");
+    if (p > 0 && (!dgamma || !dbeta)) return fail(QAOA_ERR_INVALID_ARGUMENT, "gradient output is NULL");
+    if (noalloc_need(h, p) > cap) {
+        char buf[256];
+        std::snprintf(buf, sizeof buf,
+                      "n = %d needs %zu bytes of scratch, more than the %zu of the no-allocation gradient",
+                      h->n, noalloc_need(h, p), cap);
+        g_err = buf;
+        return QAOA_ERR_INVALID_ARGUMENT;
+    }
+    return QAOA_OK;
+}
+
+qaoa_status gradient_on_scratch(qaoa_handle h, int32_t p, const double *gamma, const double *beta,
+                                double *E, double *dgamma, double *dbeta, int32_t out_is_device,
+                                void *scratch)
+{
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return device_fail(h, "hipSetDevice", hipErrorInvalidDevice);
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    char *base = (char *)scratch;
+    h->state_valid = false;
+    // No timing events here (creating them may allocate); restored on every path.
+    struct ProfOff {
+        qaoa_handle h;
+        bool was;
+        ~ProfOff() { h->profiling = was; }
+    } prof{h, h->profiling};
+    h->profiling = false;
+    double *res;
+    int nslots;
+    if (p == 0) {
+        const uint64_t T0 = (h->N + kTile - 1) / kTile;
+        double *parts = (double *)base;
+        res = (double *)(base + al(T0 * sizeof(double)));
+        nslots = 1;
+        HIPCHECK(h, launch_fill_plus(c64(h), h->psi, h->n, h->stream));
+        HIPCHECK(h, launch_expect(c64(h), h->psi, h->cost, h->n, parts, h->stream));
+        HIPCHECK(h, launch_sum_slots(parts, T0, T0, 1, res, h->stream));
+    } else {
+        const uint64_t T = nblocks(h);
+        nslots = 2 * p + 1;
+        void *lam = base;
+        double *parts = (double *)(base + al(h->N * amp_bytes(h->prec)));
+        res = (double *)((char *)parts + al((size_t)nslots * T * sizeof(double)));
+        qaoa_status st = enqueue_gradient(h, p, gamma, beta, lam, parts);
+        if (st != QAOA_OK) return st;
+        HIPCHECK(h, launch_sum_slots(parts, T, T, nslots, res, h->stream));
+    }
+    if (out_is_device) {
+        HIPCHECK(h, launch_gradient_out(res, p, E, dgamma, dbeta, h->stream));
+        return QAOA_OK;
+    }
+    double r[2 * kNoAllocMaxLayers + 1];
+    HIPCHECK(h, hipMemcpyAsync(r, res, (size_t)nslots * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    if (E) *E = r[0];
+    for (int l = 0; l < p; ++l) {
+        dbeta[l] = 2.0 * r[1 + l];
+        dgamma[l] = 2.0 * r[1 + p + l];
+    }
+    return QAOA_OK;
+}
+
+}  // namespace qk
+
 extern "C" {
 
 qaoa_status qaoa_create_maxcut(int32_t n, int64_t m, const int32_t *edges, const double *w,

@@ -103,6 +103,17 @@ __global__ __launch_bounds__(kThreads) void k_sum_slots(const double *parts, uin
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
+// Gradient outputs in device memory from the summed slots (p <= 64 threads).
+__global__ void k_gradient_out(const double *res, int p, double *E, double *dg, double *db)
+{
+    const int i = threadIdx.x;
+    if (i == 0 && E) E[0] = res[0];
+    if (i < p) {
+        db[i] = 2.0 * res[1 + i];
+        dg[i] = 2.0 * res[1 + p + i];
+    }
+}
+
 // Expectation of a stored state: one partial per 4096 amplitudes.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_expect(const typename Tr<R>::V *psi,
@@ -488,6 +499,14 @@ hipError_t launch_sum_slots(const double *parts, uint64_t count, uint64_t stride
                             double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_sum_slots, dim3(nslots), dim3(kThreads), 0, s, parts, count, stride, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gradient_out(const double *res, int p, double *E, double *dgamma, double *dbeta,
+                               hipStream_t s)
+{
+    if (p > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gradient_out, dim3(1), dim3(64), 0, s, res, p, E, dgamma, dbeta);
     return hipGetLastError();
 }
 

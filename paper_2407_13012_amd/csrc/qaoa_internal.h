@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "qaoa.h"
+
 #include <string>
 #include <vector>
 
@@ -151,6 +153,23 @@ hipError_t launch_exclusive_scan(const double *in, uint64_t count, double *out, 
 hipError_t launch_shots(bool c64, const void *psi, const void *C, int n, int sbits,
                         const double *pre, uint64_t nsub, int64_t shots, uint64_t seed,
                         uint64_t *z, double *cost, hipStream_t s);
+
+// E and the gradient from the summed slots: E = res[0], dbeta[l] = 2 res[1 + l],
+// dgamma[l] = 2 res[1 + p + l] (device pointers; E may be NULL).
+hipError_t launch_gradient_out(const double *res, int p, double *E, double *dgamma, double *dbeta,
+                               hipStream_t s);
+
+// No-allocation gradient (qaoa_gradient_noalloc): the caller supplies device
+// scratch for the adjoint vector, the partial sums and the summed slots.
+constexpr int kNoAllocMaxLayers = 32;
+int handle_device(qaoa_handle h);
+size_t noalloc_need(qaoa_handle h, int p);  // bytes of scratch for depth p
+// Argument checks (no HIP call), including noalloc_need(h, p) <= cap.
+qaoa_status noalloc_check(qaoa_handle h, int32_t p, const double *gamma, const double *beta,
+                          const double *dgamma, const double *dbeta, size_t cap);
+qaoa_status gradient_on_scratch(qaoa_handle h, int32_t p, const double *gamma, const double *beta,
+                                double *E, double *dgamma, double *dbeta, int32_t out_is_device,
+                                void *scratch);
 
 // Message reported by qaoa_last_error_message (thread-local, shared by all calls).
 void set_error_message(const std::string &m);
