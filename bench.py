@@ -155,15 +155,20 @@ def batch_bytes_per_amp(n: int, p: int, kmax: int = 10) -> float:
     """Algorithmic bytes per amplitude of one batched-engine E+G (complex128, fp64 C).
     With P mixer sweeps per layer the engine runs, forward, an init + phase sweep
     (s + c), plain sweeps (2s) and, for P >= 2, p - 1 layer-boundary sweeps
-    (2s + c; for P = 1 every later layer's sweep applies its phase: 2s + c); one
-    sweep forming E and lam = C psi (2s + c); backward the mirror image (plain 4s,
+    (2s + c; for P = 1 every later layer's sweep applies its phase: 2s + c), up
+    to the last group; the turn sweep (last group, E, lam = C phi: 2s + c, only c
+    when it is the whole evolution); backward the mirror image (plain 4s,
     boundary or phase sweeps 4s + c, the last one storing nothing: 2s + c)."""
     s, c = 16, 8
-    P = 1 if n <= 12 else 1 + -(-(n - 12) // kmax)
-    sweeps = P + (p - 1) * (P - 1) if P > 1 else p
-    phase_sweeps = p - 1                      # boundary sweeps, or later layers' phase sweeps at P = 1
-    fwd = (s + c) + phase_sweeps * (2 * s + c) + (sweeps - 1 - phase_sweeps) * 2 * s
-    bwd = (2 * s + c) + phase_sweeps * (4 * s + c) + (sweeps - 1 - phase_sweeps) * 4 * s
+    if n <= 12:  # one sweep per layer
+        if p == 1:
+            return float(c)
+        return (s + c) + (p - 2) * (2 * s + c) + (2 * s + c) + (p - 2) * (4 * s + c) + (2 * s + c)
+    P = 1 + -(-(n - 12) // kmax)
+    sweeps = P + (p - 1) * (P - 1)            # forward sweeps, the turn included
+    plain = sweeps - 2 - (p - 1)
+    fwd = (s + c) + (p - 1) * (2 * s + c) + plain * 2 * s
+    bwd = (p - 1) * (4 * s + c) + (2 * s + c) + plain * 4 * s
     return fwd + (2 * s + c) + bwd
 
 

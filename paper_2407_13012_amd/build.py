@@ -14,6 +14,18 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libqaoa.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "batch.hip", "mpnn.hip", "api.cpp", "plan.cpp", "lbfgs.cpp", "cost_terms.cpp", "noalloc.hip")]
+# passes.hip is compiled once per precision and spectator class (see its header)
+PASS_SOURCE = os.path.join(HERE, "csrc", "passes.hip")
+PASS_VARIANTS = [(real, sp) for real in ("double", "float") for sp in (-1, 0, 2, 3, 4, 5, 6, 7)]
+
+
+def units() -> list[tuple[str, list[str], str]]:
+    """(source, extra flags, object name) of every translation unit."""
+    out = [(s, [], os.path.basename(s) + ".o") for s in SOURCES]
+    for real, sp in PASS_VARIANTS:
+        tag = f"{'c128' if real == 'double' else 'c64'}_{'rt' if sp < 0 else 's%d' % sp}"
+        out.append((PASS_SOURCE, [f"-DQK_PASS_REAL={real}", f"-DQK_PASS_SP={sp}"], f"passes_{tag}.o"))
+    return out
 ARCH = os.environ.get("QAOA_OFFLOAD_ARCH", "gfx950")
 
 
@@ -28,10 +40,11 @@ def compile_flags() -> list[str]:
 
 
 def build(verbose: bool = False, jobs: int = 0) -> str:
-    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
+    jobs = jobs or min(len(units()), os.cpu_count() or 1)
     with tempfile.TemporaryDirectory(prefix="qaoa_build_") as tmpd:
-        objs = [os.path.join(tmpd, os.path.basename(s) + ".o") for s in SOURCES]
-        cmds = [["hipcc", *compile_flags(), "-c", s, "-o", o] for s, o in zip(SOURCES, objs)]
+        us = units()
+        objs = [os.path.join(tmpd, o) for _, _, o in us]
+        cmds = [["hipcc", *compile_flags(), *fl, "-c", s, "-o", o] for (s, fl, _), o in zip(us, objs)]
         if verbose:
             for c in cmds:
                 print(" ".join(c), flush=True)

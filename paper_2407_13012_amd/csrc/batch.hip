@@ -198,28 +198,33 @@ __device__ __forceinline__ int group_at(int l, int idx, int P) { return (l % 2 =
 
 // E (out[0]) and, with grad, dE/dgamma (out[1 .. p]) and dE/dbeta (out[p+1 ..])
 // of the instance in the workgroup's slot; th = (gamma, beta).  out is shared
-// memory written by thread 0.  Schedule (Sec. II-B / IV-C): the p layers
-// forward; E and lam = C psi in one elementwise sweep; then per layer, last
-// first, the mixer passes undone on (phi, lam) with the <lam|X_j|phi> terms,
-// the last of them also undoing the phase with the <lam|C|phi> term.
+// memory written by thread 0.  Schedule (Sec. II-B / IV-C), the one of the
+// single-instance gradient: the layers forward, except the last group of the
+// last layer; the turn pass, which applies that group, takes E, forms
+// lam = C psi and undoes the group on lam; then per layer, last first, the
+// mixer groups undone on (phi, lam) with the <lam|X_j|phi> terms, a layer's
+// first group also undoing its phase with the <lam|C|phi> term.  Layers visit
+// their groups in alternating order, so that with two or more groups per
+// layer the groups meeting at a layer boundary share one sweep.  Without
+// grad the forward runs through every group and its last pass takes E.
 __device__ __forceinline__ void wg_eval(const BatchArgs &B, int n, bool grad, const double *th,
                                         double2 *lds, double2 *psi, double2 *lam, double *cost,
                                         double *out)
 {
     const int p = B.p, P = uni(B.npass[n]);
-    const uint64_t N = 1ull << n;
     const uint64_t T = n > kTileBits ? 1ull << (n - kTileBits) : 1ull;
     const uint32_t tid = threadIdx.x;
+    if (tid == 0)
+        for (int i = 0; i <= 2 * p; ++i) out[i] = 0.0;
     PassArgs a;
-    // Layers visit their mixer groups in alternating order, so that with two or
-    // more groups per layer the groups meeting at a layer boundary share one
-    // sweep (the single-instance schedule, without the turn pass).
     for (int l = 0; l < p; ++l) {
         for (int idx = 0; idx < P; ++idx) {
-            if (P > 1 && l > 0 && idx == 0) continue;
+            if (P > 1 && l > 0 && idx == 0) continue;  // applied by layer l - 1's boundary sweep
+            const bool lastg = idx == P - 1;
+            if (grad && lastg && l == p - 1) break;   // the turn pass
             const int gi = P > 1 ? group_at(l, idx, P) : 0;
             make_args(a, B, n, gi, uni(th[p + l]), psi, lam, cost);
-            if (P > 1 && idx == P - 1 && l < p - 1) {
+            if (P > 1 && lastg && l < p - 1) {
                 make_second(a, uni(th[p + l + 1]));
                 a.gamma_in = uni(th[l + 1]);
                 double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -231,29 +236,35 @@ __device__ __forceinline__ void wg_eval(const BatchArgs &B, int n, bool grad, co
                 a.gamma_in = uni(th[l]);
                 if (l == 0) a.flags |= kInit;
             }
+            if (lastg && l == p - 1) a.flags |= kEOut;
             double acc[3] = {0.0, 0.0, 0.0};
             run_tiles<kFwd>(a, T, lds, acc);
+            if (tid == 0 && lastg && l == p - 1) out[0] = acc[0];
         }
     }
-    // E = sum_z C |psi|^2, and lam = C psi (the start of the reverse sweep)
-    double e = 0.0;
-    for (uint64_t z = tid; z < N; z += kThreads) {
-        const double c = cost[z];
-        const double2 v = psi[z];
-        e += c * (v.x * v.x + v.y * v.y);
-        if (grad) lam[z] = make_double2(c * v.x, c * v.y);
-    }
-    e = block_sum(e, (double *)lds);
-    if (tid == 0) {
-        out[0] = e;
-        for (int i = 1; i <= 2 * p; ++i) out[i] = 0.0;
-    }
     if (!grad) return;
-    __syncthreads();  // lam stores visible to the passes
+    {
+        const int l = p - 1;
+        make_args(a, B, n, P > 1 ? group_at(l, P - 1, P) : 0, uni(th[p + l]), psi, lam, cost);
+        double acc[3] = {0.0, 0.0, 0.0};
+        if (P == 1) {
+            a.flags |= kPhaseIn | kPhaseOut;
+            a.gamma_in = a.gamma_out = uni(th[l]);
+            if (l == 0) a.flags |= kInit | kNoStore;
+            run_tiles<kTurnPhase>(a, T, lds, acc);
+        } else {
+            run_tiles<kTurn>(a, T, lds, acc);
+        }
+        if (tid == 0) {
+            out[0] = acc[0];
+            out[1 + p + l] += acc[1];
+            out[1 + l] += acc[2];
+        }
+    }
     for (int l = p - 1; l >= 0; --l) {
         for (int j = 0; j < P; ++j) {
             const int idx = P - 1 - j;
-            if (P > 1 && j == 0 && l < p - 1) continue;  // done with layer l + 1's boundary sweep
+            if (j == 0 && (l == p - 1 || P > 1)) continue;  // the turn pass, or layer l + 1's boundary sweep
             const int gi = P > 1 ? group_at(l, idx, P) : 0;
             make_args(a, B, n, gi, uni(th[p + l]), psi, lam, cost);
             if (P > 1 && idx == 0 && l > 0) {

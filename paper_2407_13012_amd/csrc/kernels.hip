@@ -44,51 +44,6 @@
 namespace qk {
 namespace {
 
-// Two workgroups per CU (their LDS tiles fill it): 8 waves per CU for
-// complex128, 16 for complex64, whose registers are capped accordingly.  The
-// one-pass turn (n <= TB) runs a single workgroup and keeps the full register file.
-template <typename R, int MODE, bool TM>
-__global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(MODE == kTurnPhase ? 1 : Tr<R>::MINW))) void k_pass(PassArgs a)
-{
-    __shared__ typename Tr<R>::V lds[kLdsTotal<R>];
-    const uint64_t b = blockIdx.x;
-    // 2^G consecutive tiles per XCD: workgroups are dealt to the 8 XCDs in turn
-    const uint32_t G = a.xcd_g;
-    const uint64_t t = G ? ((b & ~((8ull << G) - 1ull)) | ((b & 7ull) << G) | ((b >> 3) & ((1ull << G) - 1ull)))
-                         : b;
-    double sums[4];
-    tile_pass<R, MODE, TM>(a, t, lds, sums);
-    // one partial per workgroup
-    if (threadIdx.x == 0) {
-        if (MODE == kTurn || MODE == kTurnPhase || (MODE == kFwd && (a.flags & kEOut))) a.part_e[b] = sums[0];
-        if (MODE != kFwd) a.part_b[b] = (a.flags & kBetaAcc) ? a.part_b[b] + sums[1] : sums[1];
-        if (MODE == kTurnPhase || (MODE == kBwd && (a.flags & kPhaseOut))) a.part_g[b] = sums[2];
-    }
-}
-
-// Layer-boundary passes (kFwdFuse, kBwdFuse); TM / TM2 are the factored forms
-// of the two rotations.  Same tile order and partial layout as k_pass.
-template <typename R, int MODE, bool TM, bool TM2>
-__global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>::MINW))) void k_pass_fuse(PassArgs a)
-{
-    __shared__ typename Tr<R>::V lds[kLdsTotal<R>];
-    const uint64_t b = blockIdx.x;
-    const uint32_t G = a.xcd_g;
-    const uint64_t t = G ? ((b & ~((8ull << G) - 1ull)) | ((b & 7ull) << G) | ((b >> 3) & ((1ull << G) - 1ull)))
-                         : b;
-    if constexpr (MODE == kFwdFuse) {
-        tile_pass_fwd_fuse<R, TM, TM2>(a, t, lds);
-    } else {
-        double sums[4];
-        tile_pass<R, kBwdFuse, TM, TM2>(a, t, lds, sums);
-        if (threadIdx.x == 0) {
-            a.part_b[b] = (a.flags & kBetaAcc) ? a.part_b[b] + sums[1] : sums[1];
-            a.part_g[b] = sums[2];
-            a.part_b2[b] = (a.flags & kBetaAcc2) ? a.part_b2[b] + sums[3] : sums[3];
-        }
-    }
-}
-
 // ------------------------------------------------------------ reductions
 
 // out[k] = sum_{i < count} parts[k * stride + i], one workgroup per slot, fixed order.
@@ -450,49 +405,49 @@ inline unsigned grid_for(uint64_t N, uint64_t cap = 1ull << 20)
 
 // ------------------------------------------------------------ launchers
 
-template <typename R, bool TM>
-static void launch_pass_t(int mode, const PassArgs &a, dim3 grid, hipStream_t s)
+int static_spectators(const Geometry &g, bool c64, int mode)
 {
-    const dim3 block(Tr<R>::NT);
-    if (mode == kFwd) hipLaunchKernelGGL((k_pass<R, kFwd, TM>), grid, block, 0, s, a);
-    else if (mode == kTurn) hipLaunchKernelGGL((k_pass<R, kTurn, TM>), grid, block, 0, s, a);
-    else if (mode == kTurnPhase)
-        hipLaunchKernelGGL((k_pass<R, kTurnPhase, TM>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_pass<R, kBwd, TM>), grid, block, 0, s, a);
+    const int TB = tile_bits(c64);
+    const uint32_t t = g.tmask;
+    if ((int)g.tbits != TB || t == 0) return -1;
+    const int S = __builtin_ctz(t);
+    if (t != (((1u << TB) - 1u) & ~((1u << S) - 1u))) return -1;  // not "every bit from S up"
+    // complex64 layer-boundary backward sweeps keep the run-time mask: with the
+    // stages fixed the compiler spills about 30 registers in them (128 allowed)
+    // and the sweep ran 17 % slower (51.6 vs 44.1 ms at n = 32)
+    if (c64 && mode == kBwdFuse) return -1;
+    if (S == 0) return 0;
+    return (S >= 2 && S <= 7 && mode != kTurnPhase) ? S : -1;
 }
 
-template <typename R, int MODE>
-static void launch_fuse_t(const PassArgs &a, dim3 grid, hipStream_t s)
-{
-    const dim3 block(Tr<R>::NT);
-    const int sel = (a.tan_mode ? 2 : 0) + (a.tan_mode2 ? 1 : 0);
-    if (sel == 3) hipLaunchKernelGGL((k_pass_fuse<R, MODE, true, true>), grid, block, 0, s, a);
-    else if (sel == 2) hipLaunchKernelGGL((k_pass_fuse<R, MODE, true, false>), grid, block, 0, s, a);
-    else if (sel == 1) hipLaunchKernelGGL((k_pass_fuse<R, MODE, false, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_pass_fuse<R, MODE, false, false>), grid, block, 0, s, a);
-}
-
+// A pass with a spectator class that has its own kernels (every full-tile pass
+// whose S lowest tile bits are spectators, S = 0 or 2..7) runs them;
+// any other pass runs the kernels that read the target mask at run time.
 hipError_t launch_pass(int mode, bool c64, const PassArgs &a, uint64_t nblocks, hipStream_t s)
 {
-    const dim3 grid((unsigned)nblocks);
-    if (mode == kFwdFuse || mode == kBwdFuse) {
-        if (!c64) {
-            if (mode == kFwdFuse) launch_fuse_t<double, kFwdFuse>(a, grid, s);
-            else launch_fuse_t<double, kBwdFuse>(a, grid, s);
-        } else {
-            if (mode == kFwdFuse) launch_fuse_t<float, kFwdFuse>(a, grid, s);
-            else launch_fuse_t<float, kBwdFuse>(a, grid, s);
-        }
-        return hipGetLastError();
-    }
+    const int sp = static_spectators(a.geo, c64, mode);
     if (!c64) {
-        if (a.tan_mode) launch_pass_t<double, true>(mode, a, grid, s);
-        else launch_pass_t<double, false>(mode, a, grid, s);
-    } else {
-        if (a.tan_mode) launch_pass_t<float, true>(mode, a, grid, s);
-        else launch_pass_t<float, false>(mode, a, grid, s);
+        switch (sp) {
+        case 0: return launch_pass_sp<double, 0>(mode, a, nblocks, s);
+        case 2: return launch_pass_sp<double, 2>(mode, a, nblocks, s);
+        case 3: return launch_pass_sp<double, 3>(mode, a, nblocks, s);
+        case 4: return launch_pass_sp<double, 4>(mode, a, nblocks, s);
+        case 5: return launch_pass_sp<double, 5>(mode, a, nblocks, s);
+        case 6: return launch_pass_sp<double, 6>(mode, a, nblocks, s);
+        case 7: return launch_pass_sp<double, 7>(mode, a, nblocks, s);
+        default: return launch_pass_sp<double, -1>(mode, a, nblocks, s);
+        }
     }
-    return hipGetLastError();
+    switch (sp) {
+    case 0: return launch_pass_sp<float, 0>(mode, a, nblocks, s);
+    case 2: return launch_pass_sp<float, 2>(mode, a, nblocks, s);
+    case 3: return launch_pass_sp<float, 3>(mode, a, nblocks, s);
+    case 4: return launch_pass_sp<float, 4>(mode, a, nblocks, s);
+    case 5: return launch_pass_sp<float, 5>(mode, a, nblocks, s);
+    case 6: return launch_pass_sp<float, 6>(mode, a, nblocks, s);
+    case 7: return launch_pass_sp<float, 7>(mode, a, nblocks, s);
+    default: return launch_pass_sp<float, -1>(mode, a, nblocks, s);
+    }
 }
 
 hipError_t launch_sum_slots(const double *parts, uint64_t count, uint64_t stride, int nslots,

@@ -1,0 +1,121 @@
+// Pass kernels (k_pass, k_pass_fuse) of one precision and one spectator class.
+//
+// This file is compiled once per (QK_PASS_REAL, QK_PASS_SP): QK_PASS_REAL is
+// double (complex128 tiles) or float (complex64 tiles), QK_PASS_SP the number
+// S of spectator tile bits the kernels assume (the S lowest tile bits are not
+// rotated, every other tile bit is), or -1 for kernels that read the pass's
+// target mask at run time.  With S fixed every rotation stage of the tile code
+// is taken or left out at compile time: a stage under a run-time branch leaves
+// its results in new registers and the join after it copies them back, about
+// a quarter of the VALU work of a two-vector pass.  The tile code itself (load,
+// phase, rotations, transposes, reductions, stores) is in tile_device.h; the
+// kernels and the host launcher of each translation unit are its own.
+#include "tile_device.h"
+
+#ifndef QK_PASS_REAL
+#error "QK_PASS_REAL (double or float) must be defined"
+#endif
+#ifndef QK_PASS_SP
+#error "QK_PASS_SP (spectator class, -1 for the run-time mask) must be defined"
+#endif
+
+namespace qk {
+namespace {
+
+// Two workgroups per CU (their LDS tiles fill it): 8 waves per CU for
+// complex128, 16 for complex64, whose registers are capped accordingly.  The
+// one-pass turn (n <= TB) runs a single workgroup and keeps the full register file.
+template <typename R, int MODE, bool TM, int SP>
+__global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(MODE == kTurnPhase ? 1 : Tr<R>::MINW))) void k_pass(PassArgs a)
+{
+    __shared__ typename Tr<R>::V lds[kLdsTotal<R>];
+    const uint64_t b = blockIdx.x;
+    // 2^G consecutive tiles per XCD: workgroups are dealt to the 8 XCDs in turn
+    const uint32_t G = a.xcd_g;
+    const uint64_t t = G ? ((b & ~((8ull << G) - 1ull)) | ((b & 7ull) << G) | ((b >> 3) & ((1ull << G) - 1ull)))
+                         : b;
+    double sums[4];
+    tile_pass<R, MODE, TM, TM, SP>(a, t, lds, sums);
+    // one partial per workgroup
+    if (threadIdx.x == 0) {
+        if (MODE == kTurn || MODE == kTurnPhase || (MODE == kFwd && (a.flags & kEOut))) a.part_e[b] = sums[0];
+        if (MODE != kFwd) a.part_b[b] = (a.flags & kBetaAcc) ? a.part_b[b] + sums[1] : sums[1];
+        if (MODE == kTurnPhase || (MODE == kBwd && (a.flags & kPhaseOut))) a.part_g[b] = sums[2];
+    }
+}
+
+// Layer-boundary passes (kFwdFuse, kBwdFuse); TM / TM2 are the factored forms
+// of the two rotations.  Same tile order and partial layout as k_pass.
+template <typename R, int MODE, bool TM, bool TM2, int SP>
+__global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>::MINW))) void k_pass_fuse(PassArgs a)
+{
+    __shared__ typename Tr<R>::V lds[kLdsTotal<R>];
+    const uint64_t b = blockIdx.x;
+    const uint32_t G = a.xcd_g;
+    const uint64_t t = G ? ((b & ~((8ull << G) - 1ull)) | ((b & 7ull) << G) | ((b >> 3) & ((1ull << G) - 1ull)))
+                         : b;
+    if constexpr (MODE == kFwdFuse) {
+        tile_pass_fwd_fuse<R, TM, TM2, SP>(a, t, lds);
+    } else {
+        double sums[4];
+        tile_pass<R, kBwdFuse, TM, TM2, SP>(a, t, lds, sums);
+        if (threadIdx.x == 0) {
+            a.part_b[b] = (a.flags & kBetaAcc) ? a.part_b[b] + sums[1] : sums[1];
+            a.part_g[b] = sums[2];
+            a.part_b2[b] = (a.flags & kBetaAcc2) ? a.part_b2[b] + sums[3] : sums[3];
+        }
+    }
+}
+
+template <typename R, bool TM, int SP>
+void launch_single(int mode, const PassArgs &a, dim3 grid, hipStream_t s)
+{
+    const dim3 block(Tr<R>::NT);
+    if (mode == kFwd) hipLaunchKernelGGL((k_pass<R, kFwd, TM, SP>), grid, block, 0, s, a);
+    else if (mode == kTurn) hipLaunchKernelGGL((k_pass<R, kTurn, TM, SP>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_pass<R, kBwd, TM, SP>), grid, block, 0, s, a);
+}
+
+template <typename R, int MODE, int SP>
+void launch_fuse(const PassArgs &a, dim3 grid, hipStream_t s)
+{
+    const dim3 block(Tr<R>::NT);
+    const int sel = (a.tan_mode ? 2 : 0) + (a.tan_mode2 ? 1 : 0);
+    if (sel == 3) hipLaunchKernelGGL((k_pass_fuse<R, MODE, true, true, SP>), grid, block, 0, s, a);
+    else if (sel == 2) hipLaunchKernelGGL((k_pass_fuse<R, MODE, true, false, SP>), grid, block, 0, s, a);
+    else if (sel == 1) hipLaunchKernelGGL((k_pass_fuse<R, MODE, false, true, SP>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_pass_fuse<R, MODE, false, false, SP>), grid, block, 0, s, a);
+}
+
+}  // namespace
+
+template <typename R, int SP>
+hipError_t launch_pass_sp(int mode, const PassArgs &a, uint64_t nblocks, hipStream_t s)
+{
+    const dim3 grid((unsigned)nblocks);
+    if (mode == kFwdFuse) {
+        launch_fuse<R, kFwdFuse, SP>(a, grid, s);
+    } else if (mode == kBwdFuse) {
+        // complex64 layer-boundary backward sweeps run the run-time-mask kernels
+        // (static_spectators)
+        if constexpr (std::is_same<R, float>::value && SP >= 0) return hipErrorInvalidValue;
+        else launch_fuse<R, kBwdFuse, SP>(a, grid, s);
+    } else if (mode == kTurnPhase) {
+        // the one-pass turn (n <= TB): its tile holds every qubit, no spectators
+        if constexpr (SP > 0) return hipErrorInvalidValue;
+        else {
+            const dim3 block(Tr<R>::NT);
+            if (a.tan_mode) hipLaunchKernelGGL((k_pass<R, kTurnPhase, true, SP>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_pass<R, kTurnPhase, false, SP>), grid, block, 0, s, a);
+        }
+    } else if (a.tan_mode) {
+        launch_single<R, true, SP>(mode, a, grid, s);
+    } else {
+        launch_single<R, false, SP>(mode, a, grid, s);
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_pass_sp<QK_PASS_REAL, QK_PASS_SP>(int, const PassArgs &, uint64_t, hipStream_t);
+
+}  // namespace qk

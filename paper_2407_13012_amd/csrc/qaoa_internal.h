@@ -106,6 +106,14 @@ struct PassArgs {
 
 // Launchers; all return the launch status.  `c64` selects complex64/fp32 cost.
 hipError_t launch_pass(int mode, bool c64, const PassArgs &a, uint64_t nblocks, hipStream_t s);
+// Pass kernels of one precision (R = double: complex128, float: complex64)
+// and spectator class SP (passes.hip, one translation unit per pair): SP >= 0
+// for full-tile passes that rotate every tile bit from SP up, -1 for the
+// kernels that read the target mask at run time.
+template <typename R, int SP>
+hipError_t launch_pass_sp(int mode, const PassArgs &a, uint64_t nblocks, hipStream_t s);
+// Spectator class of a pass with kernels of its own (0 or 2..7), else -1.
+int static_spectators(const Geometry &g, bool c64, int mode);
 hipError_t launch_sum_slots(const double *parts, uint64_t count, uint64_t stride, int nslots,
                             double *out, hipStream_t s);
 

@@ -25,7 +25,7 @@ struct Tr<double> {
     static constexpr int NW = 1 << WB;
     static constexpr int NT = 64 * NW;
     static constexpr int NR = 16;
-    static constexpr int MINW = 1;  // waves per SIMD the pass kernels must allow
+    static constexpr int MINW = 2;  // waves per SIMD the pass kernels must allow (two workgroups per CU)
 };
 template <>
 struct Tr<float> {
@@ -226,35 +226,68 @@ struct PairSum<float2> {
 // split into two 33-bit parts and a remainder (k pi/2 is exact for |k| < 2^20),
 // then the Taylor series of sin (to r^17) and cos (to r^18) on |r| <= pi/4,
 // whose truncation error is below 1e-19.  Larger arguments use the library.
-__device__ __forceinline__ void sincos_cw(double x, double &s, double &c)
+//
+// The fp64 constants are held in scalar registers for a whole loop over a
+// thread's amplitudes (PhaseK, built once per loop by phase_consts()): an fp64
+// operand that is not an inline constant would otherwise be rebuilt in vector
+// registers, two moves per constant, for every amplitude.
+struct PhaseK {
+    double k[20];
+};
+struct PhaseK32 {};  // complex64: no fp64 polynomial constants
+template <typename R>
+__device__ __forceinline__ PhaseK32 phase_consts(std::enable_if_t<std::is_same<R, float>::value, int> = 0)
+{
+    return {};
+}
+template <typename R>
+__device__ __forceinline__ PhaseK phase_consts(std::enable_if_t<std::is_same<R, double>::value, int> = 0)
+{
+    PhaseK K = {{
+        0x1.45f306dc9c883p-1,    // 2/pi
+        0x1.921fb54400000p+0,    // pi/2: leading 33 bits
+        0x1.0b4611a600000p-34,   //       next 33 bits
+        0x1.3198a2e037073p-69,   //       remainder
+        2.8114572543455206e-15,  //  1/17!   sin r / r - 1 in powers of r^2, highest first
+        -7.647163731819816e-13,  // -1/15!
+        1.6059043836821613e-10,  //  1/13!
+        -2.505210838544172e-08,  // -1/11!
+        2.7557319223985893e-06,  //  1/9!
+        -0.0001984126984126984,  // -1/7!
+        0.008333333333333333,    //  1/5!
+        -0.16666666666666666,    // -1/3!
+        -1.5619206968586225e-16, // -1/18!   cos r in powers of r^2, highest first
+        4.779477332387385e-14,   //  1/16!
+        -1.1470745597729725e-11, // -1/14!
+        2.08767569878681e-09,    //  1/12!
+        -2.755731922398589e-07,  // -1/10!
+        2.48015873015873e-05,    //  1/8!
+        -0.001388888888888889,   // -1/6!
+        0.041666666666666664,    //  1/4!   (then -1/2! and 1 are inline constants)
+    }};
+#pragma unroll
+    for (int i = 0; i < 20; ++i) asm volatile("" : "+s"(K.k[i]));
+    return K;
+}
+__device__ __forceinline__ void sincos_cw(double x, double &s, double &c, const PhaseK &K)
 {
     if (!(fabs(x) < 1.0e6)) {
         sincos(x, &s, &c);
         return;
     }
-    const double k = rint(x * 0x1.45f306dc9c883p-1);  // 2/pi
-    double r = fma(-k, 0x1.921fb54400000p+0, x);
-    r = fma(-k, 0x1.0b4611a600000p-34, r);
-    r = fma(-k, 0x1.3198a2e037073p-69, r);
+    const double k = rint(x * K.k[0]);
+    double r = fma(-k, K.k[1], x);
+    r = fma(-k, K.k[2], r);
+    r = fma(-k, K.k[3], r);
     const double r2 = r * r;
-    double ps = 2.8114572543455206e-15;  //  1/17!
-    ps = fma(ps, r2, -7.647163731819816e-13);   // -1/15!
-    ps = fma(ps, r2, 1.6059043836821613e-10);   //  1/13!
-    ps = fma(ps, r2, -2.505210838544172e-08);   // -1/11!
-    ps = fma(ps, r2, 2.7557319223985893e-06);   //  1/9!
-    ps = fma(ps, r2, -0.0001984126984126984);   // -1/7!
-    ps = fma(ps, r2, 0.008333333333333333);     //  1/5!
-    ps = fma(ps, r2, -0.16666666666666666);     // -1/3!
+    double ps = K.k[4];
+#pragma unroll
+    for (int i = 5; i < 12; ++i) ps = fma(ps, r2, K.k[i]);
     const double sr = fma(ps * r2, r, r);
-    double pc = -1.5619206968586225e-16;  // -1/18!
-    pc = fma(pc, r2, 4.779477332387385e-14);    //  1/16!
-    pc = fma(pc, r2, -1.1470745597729725e-11);  // -1/14!
-    pc = fma(pc, r2, 2.08767569878681e-09);     //  1/12!
-    pc = fma(pc, r2, -2.755731922398589e-07);   // -1/10!
-    pc = fma(pc, r2, 2.48015873015873e-05);     //  1/8!
-    pc = fma(pc, r2, -0.001388888888888889);    // -1/6!
-    pc = fma(pc, r2, 0.041666666666666664);     //  1/4!
-    pc = fma(pc, r2, -0.5);                     // -1/2!
+    double pc = K.k[12];
+#pragma unroll
+    for (int i = 13; i < 20; ++i) pc = fma(pc, r2, K.k[i]);
+    pc = fma(pc, r2, -0.5);
     const double cr = fma(pc, r2, 1.0);
     const int q = (int)(((long long)k) & 3);
     // x = k pi/2 + r: rotate (cos r, sin r) by q quarter turns
@@ -269,12 +302,13 @@ __device__ __forceinline__ void sincos_cw(double x, double &s, double &c)
 // r^8 are summed in fp32 (truncation below 3e-8, under half an fp32 ulp of
 // cos r >= 0.7).  r is clamped to [-pi/4, pi/4], so even arguments too large
 // for the reduction (|x| beyond ~2^50, far past fp32 phase resolution) give a
-// unit-modulus factor.
-__device__ __forceinline__ void phase_cs(double g, double cval, double &c, double &s)
+// unit-modulus factor.  K holds the constants of the complex128 form (the
+// complex64 form needs none beyond fp32 literals and a few fp64 ones).
+__device__ __forceinline__ void phase_cs(double g, double cval, double &c, double &s, const PhaseK &K)
 {
-    sincos_cw(g * cval, s, c);
+    sincos_cw(g * cval, s, c, K);
 }
-__device__ __forceinline__ void phase_cs(double g, float cval, float &c, float &s)
+__device__ __forceinline__ void phase_cs(double g, float cval, float &c, float &s, const PhaseK32 &)
 {
     const double th = g * (double)cval;
     const double k = rint(th * 0.6366197723675814);  // 2/pi
@@ -354,20 +388,50 @@ __device__ __forceinline__ void bfly_lane(V &s, V p, R m)
     }
 }
 
-template <int ARR, bool TM, typename V, typename R>
-__device__ __forceinline__ void mix_stage(V (&v)[16], R m, uint32_t tmask)
+// Target bits of a pass as the stages see them.  Every full-tile pass of the
+// plan rotates all tile bits from some S up (the S lowest bits are
+// spectators).  With SP = S >= 0 that is known at compile time and every stage
+// is taken or left out statically; with SP < 0 the tile-local mask decides at
+// run time under wave-uniform branches (partial tiles, other plans).
+template <int SP>
+struct Targets {
+    uint32_t tmask;
+    __device__ __forceinline__ bool has(uint32_t bit) const
+    {
+        if constexpr (SP >= 0) return bit >= (uint32_t)SP;
+        else return (tmask >> bit) & 1u;
+    }
+};
+
+// Rotations of the target bits among the register bits of arrangement ARR
+// (and, for 13-bit tiles in B, the lane-held bit 12).  Each register bit's
+// stage runs under a wave-uniform branch.  The butterflies leave their
+// results in new registers, and the values must sit in the same registers
+// wherever the taken and the skipped path meet; with SKIP_COPY an empty asm
+// statement redefines the values on the skipped path, so the register copies
+// of that join are made there (where a pass skips a bit, once per tile)
+// instead of after every taken stage: a third fewer VALU instructions in the
+// compute of a complex128 forward pass, 2-3 % off those passes' time.  It is
+// applied to complex128 tiles only (complex64 forward passes measured 11 %
+// slower with it) and not in kernels that hold a second vector beside v,
+// where it raises the register count past the kernel's budget.
+template <int ARR, bool TM, bool SKIP_COPY = false, int SP, typename V, typename R>
+__device__ __forceinline__ void mix_stage(V (&v)[16], R m, Targets<SP> tg)
 {
     constexpr int WB = kWaveBits<V>;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if ((tmask >> regbit<ARR>(q)) & 1u) {
+        if (tg.has(regbit<ARR>(q))) {
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 if (!(r & (1 << q))) bfly<TM>(v[r], v[r | (1 << q)], m);
+        } else if constexpr (SKIP_COPY && SP < 0 && std::is_same<V, double2>::value) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) asm volatile("" : "+v"(v[r].x), "+v"(v[r].y));
         }
     }
     if constexpr (ARR == 1 && WB == 3) {
-        if ((tmask >> 12) & 1u) {
+        if (tg.has(12)) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) bfly_lane<TM>(v[r], lane_partner(v[r]), m);
         }
@@ -379,14 +443,14 @@ __device__ __forceinline__ void mix_stage(V (&v)[16], R m, uint32_t tmask)
 // apply the factored inverse rotation to both.  Across lanes (tile bit 12 of
 // 13-bit tiles, arrangement B) each lane adds Im(conj(lam) phi_partner); the
 // two lanes of a pair together give the pair's term.
-template <int ARR, bool TM, typename V, typename R>
-__device__ __forceinline__ void adj_stage(V (&f)[16], V (&l)[16], R m, uint32_t tmask,
+template <int ARR, bool TM, int SP, typename V, typename R>
+__device__ __forceinline__ void adj_stage(V (&f)[16], V (&l)[16], R m, Targets<SP> tg,
                                           double &sig2, double f2, double &accB)
 {
     constexpr int WB = kWaveBits<V>;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if ((tmask >> regbit<ARR>(q)) & 1u) {
+        if (tg.has(regbit<ARR>(q))) {
             typename PairSum<V>::T ps = 0;
 #pragma unroll
             for (int r = 0; r < 16; ++r)
@@ -395,6 +459,10 @@ __device__ __forceinline__ void adj_stage(V (&f)[16], V (&l)[16], R m, uint32_t 
                     ps = imcx_acc(l[r1], f[r], imcx_acc(l[r], f[r1], ps));
                 }
             accB = fma(sig2, (double)ps, accB);
+            // The sum is formed here, while the stage's inputs are live: left to
+            // the compiler it can be sunk towards its use at the end of the tile,
+            // keeping the inputs of every stage alive (spills in straight-line code).
+            asm volatile("" : "+v"(accB));
             sig2 *= f2;
 #pragma unroll
             for (int r = 0; r < 16; ++r)
@@ -405,7 +473,7 @@ __device__ __forceinline__ void adj_stage(V (&f)[16], V (&l)[16], R m, uint32_t 
         }
     }
     if constexpr (ARR == 1 && WB == 3) {
-        if ((tmask >> 12) & 1u) {
+        if (tg.has(12)) {
             typename PairSum<V>::T ps = 0;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
@@ -415,6 +483,7 @@ __device__ __forceinline__ void adj_stage(V (&f)[16], V (&l)[16], R m, uint32_t 
                 bfly_lane<TM>(f[r], fp, m);
             }
             accB = fma(sig2, (double)ps, accB);
+            asm volatile("" : "+v"(accB));
             sig2 *= f2;
         }
     }
@@ -422,8 +491,8 @@ __device__ __forceinline__ void adj_stage(V (&f)[16], V (&l)[16], R m, uint32_t 
 
 // Sum over the target bits owned by arrangement ARR of Im<lam|X_j|phi> on the
 // register (and lane) pairs, times w (the product of the factors both vectors miss).
-template <int ARR, typename V>
-__device__ __forceinline__ void beta_terms(const V (&f)[16], const V (&l)[16], uint32_t tmask,
+template <int ARR, int SP, typename V>
+__device__ __forceinline__ void beta_terms(const V (&f)[16], const V (&l)[16], Targets<SP> tg,
                                            double w, double &accB)
 {
     constexpr int WB = kWaveBits<V>;
@@ -432,7 +501,7 @@ __device__ __forceinline__ void beta_terms(const V (&f)[16], const V (&l)[16], u
     double ps = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if ((tmask >> regbit<ARR>(q)) & 1u) {
+        if (tg.has(regbit<ARR>(q))) {
             PS pq = 0;
             if constexpr (std::is_same<PS, double>::value) pq = ps;
 #pragma unroll
@@ -446,7 +515,7 @@ __device__ __forceinline__ void beta_terms(const V (&f)[16], const V (&l)[16], u
         }
     }
     if constexpr (ARR == 1 && WB == 3) {
-        if ((tmask >> 12) & 1u) {
+        if (tg.has(12)) {
             PS pq = 0;
 #pragma unroll
             for (int r = 0; r < 16; ++r) pq = imcx_acc(l[r], lane_partner(f[r]), pq);
@@ -454,6 +523,7 @@ __device__ __forceinline__ void beta_terms(const V (&f)[16], const V (&l)[16], u
         }
     }
     accB = fma(w, ps, accB);
+    asm volatile("" : "+v"(accB));
 }
 
 __host__ __device__ __forceinline__ int popc(uint32_t x) { return __builtin_popcount(x); }
@@ -557,7 +627,7 @@ __device__ __forceinline__ void st(T v, T *p, bool stream)
 // One pass over tile t: load, [phase], rotations, [E / adjoint terms / phase
 // undo], store.  The workgroup's sums of the E, <lam|X|phi> and <lam|C|phi>
 // terms are returned in sums[0..2] (valid in thread 0; zero when not taken).
-template <typename R, int MODE, bool TM, bool TM2 = TM>
+template <typename R, int MODE, bool TM, bool TM2 = TM, int SP = -1>
 __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typename Tr<R>::V *lds,
                                           double (&sums)[4])
 {
@@ -575,7 +645,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
     const uint64_t base = tile_base(t, g);
     const bool full = g.tbits == (uint32_t)Tr<R>::TB;
     const uint32_t lim = 1u << g.tbits;
-    const uint32_t tmask = g.tmask;
+    const Targets<SP> tg{g.tmask};
     const bool strm = (a.flags & kStream) != 0;
     V *psi = (V *)a.psi;
     V *lam = (V *)a.lam;
@@ -651,11 +721,12 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
         }
         if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
         if (phaseIn) {
+            const auto PK = phase_consts<R>();
 #pragma unroll
             for (int r = 0; r < NR; ++r)
                 if (VA(r)) {
                     R c, s;
-                    phase_cs(-a.gamma_in, cin[r], c, s);
+                    phase_cs(-a.gamma_in, cin[r], c, s, PK);
                     v[r] = cmul(v[r], c, s);
                 }
         }
@@ -668,11 +739,11 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
             for (int r = 0; r < NR; ++r) v0[r] = v[r];
         }
         const R mf = (R)a.mul_f;
-        mix_stage<0, TM>(v, mf, tmask);
+        mix_stage<0, TM, !TURN>(v, mf, tg);
         xpose<0, 1>(v, lds, lane, wave);
-        mix_stage<1, TM>(v, mf, tmask);
+        mix_stage<1, TM, !TURN>(v, mf, tg);
         xpose<1, 2>(v, lds, lane, wave);
-        mix_stage<2, TM>(v, mf, tmask);
+        mix_stage<2, TM, !TURN>(v, mf, tg);
         const R sf = (R)a.scl_f;
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r] = vscale(v[r], sf);
@@ -708,11 +779,11 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                 // both vectors sit at the same point.  Arrangement C: the final point.
                 // Then undo C's rotations on lam only; phi before stage C is still in
                 // LDS from the forward B->C transpose, so it is re-read, not recomputed.
-                const int kA = popc(tmask & owned<0, WB>()), kB = popc(tmask & owned<1, WB>());
-                const int kC = popc(tmask & owned<2, WB>());
+                const int kA = popc(tg.tmask & owned<0, WB>()), kB = popc(tg.tmask & owned<1, WB>());
+                const int kC = popc(tg.tmask & owned<2, WB>());
                 const double ff = a.fac_f, fb = a.fac_b;
-                beta_terms<2>(v, l, tmask, 1.0, accB);
-                mix_stage<2, TM>(l, mb, tmask);
+                beta_terms<2>(v, l, tg, 1.0, accB);
+                mix_stage<2, TM>(l, mb, tg);
                 {
                     const V *rd = lds + lds_slot<WB>(elem<1, WB>(lane, wave, 0));
 #pragma unroll
@@ -721,20 +792,20 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                 }
                 xpose<2, 1>(l, lds, lane, wave);
                 // lam misses fb^kC, phi (forward stages A, B) misses ff^(kA+kB)
-                beta_terms<1>(v, l, tmask, upow(fb, kC) * upow(ff, kA + kB), accB);
-                mix_stage<1, TM>(l, mb, tmask);
+                beta_terms<1>(v, l, tg, upow(fb, kC) * upow(ff, kA + kB), accB);
+                mix_stage<1, TM>(l, mb, tg);
                 if constexpr (kKeep0) {
                     // A's bits at the point before the group: the loaded phi (exact)
                     // and lam with the whole group undone (missing fb^k)
                     xpose<1, 0>(l, lds, lane, wave);
-                    mix_stage<0, TM>(l, mb, tmask);
-                    beta_terms<0>(v0, l, tmask, upow(fb, kA + kB + kC), accB);
+                    mix_stage<0, TM>(l, mb, tg);
+                    beta_terms<0>(v0, l, tg, upow(fb, kA + kB + kC), accB);
                 } else {
-                    mix_stage<1, TM>(v, mb, tmask);
+                    mix_stage<1, TM>(v, mb, tg);
                     xpose<1, 0>(v, lds, lane, wave);
                     xpose<1, 0>(l, lds, lane, wave);
-                    beta_terms<0>(v, l, tmask, upow(fb, kC + 2 * kB) * upow(ff, kA + kB), accB);
-                    mix_stage<0, TM>(l, mb, tmask);
+                    beta_terms<0>(v, l, tg, upow(fb, kC + 2 * kB) * upow(ff, kA + kB), accB);
+                    mix_stage<0, TM>(l, mb, tg);
                 }
                 REDUCE();
                 if (!(a.flags & kNoStore)) {
@@ -745,22 +816,23 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
             } else {
             const double f2 = a.fac_b * a.fac_b;
             double sig2 = 1.0;
-            adj_stage<2, TM>(v, l, mb, tmask, sig2, f2, accB);
+            adj_stage<2, TM>(v, l, mb, tg, sig2, f2, accB);
             xpose<2, 1>(v, lds, lane, wave);
             xpose<2, 1>(l, lds, lane, wave);
-            adj_stage<1, TM>(v, l, mb, tmask, sig2, f2, accB);
+            adj_stage<1, TM>(v, l, mb, tg, sig2, f2, accB);
             xpose<1, 0>(v, lds, lane, wave);
             xpose<1, 0>(l, lds, lane, wave);
-            adj_stage<0, TM>(v, l, mb, tmask, sig2, f2, accB);
+            adj_stage<0, TM>(v, l, mb, tg, sig2, f2, accB);
                 xpose<0, 2>(l, lds, lane, wave);
                 xpose<0, 2>(v, lds, lane, wave);
+                const auto PK = phase_consts<R>();
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
                     l[r] = vscale(l[r], sb);
                     if (VC(r)) {
                         accG += (double)cv[r] * imcx(l[r], vscale(v[r], sb));
                         R c, s;
-                        phase_cs(a.gamma_out, cv[r], c, s);
+                        phase_cs(a.gamma_out, cv[r], c, s, PK);
                         l[r] = cmul(l[r], c, s);
                     }
                 }
@@ -784,13 +856,13 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
         const R mb = (R)a.mul_b;
         const double f2 = a.fac_b * a.fac_b;
         double sig2 = 1.0;
-        adj_stage<0, TM>(f, l, mb, tmask, sig2, f2, accB);
+        adj_stage<0, TM>(f, l, mb, tg, sig2, f2, accB);
         xpose<0, 1>(f, lds, lane, wave);
         xpose<0, 1>(l, lds, lane, wave);
-        adj_stage<1, TM>(f, l, mb, tmask, sig2, f2, accB);
+        adj_stage<1, TM>(f, l, mb, tg, sig2, f2, accB);
         xpose<1, 2>(f, lds, lane, wave);
         xpose<1, 2>(l, lds, lane, wave);
-        adj_stage<2, TM>(f, l, mb, tmask, sig2, f2, accB);
+        adj_stage<2, TM>(f, l, mb, tg, sig2, f2, accB);
         const R sb = (R)a.scl_b;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -804,13 +876,14 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
             }
             // the last sweep stores nothing, so it skips the phase undo
             const bool undo = MODE == kBwdFuse || !(a.flags & kNoStore);
+            const auto PK = phase_consts<R>();
 #pragma unroll
             for (int r = 0; r < NR; ++r)
                 if (VC(r)) {
                     accG += (double)cv[r] * imcx(l[r], f[r]);
                     if (undo) {
                         R c, s;
-                        phase_cs(a.gamma_out, cv[r], c, s);
+                        phase_cs(a.gamma_out, cv[r], c, s, PK);
                         f[r] = cmul(f[r], c, s);
                         l[r] = cmul(l[r], c, s);
                     }
@@ -821,13 +894,13 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
             const R mb2 = (R)a.mul_b2;
             const double f22 = a.fac_b2 * a.fac_b2;
             double sig22 = 1.0;
-            adj_stage<2, TM2>(f, l, mb2, tmask, sig22, f22, accB2);
+            adj_stage<2, TM2>(f, l, mb2, tg, sig22, f22, accB2);
             xpose<2, 1>(f, lds, lane, wave);
             xpose<2, 1>(l, lds, lane, wave);
-            adj_stage<1, TM2>(f, l, mb2, tmask, sig22, f22, accB2);
+            adj_stage<1, TM2>(f, l, mb2, tg, sig22, f22, accB2);
             xpose<1, 0>(f, lds, lane, wave);
             xpose<1, 0>(l, lds, lane, wave);
-            adj_stage<0, TM2>(f, l, mb2, tmask, sig22, f22, accB2);
+            adj_stage<0, TM2>(f, l, mb2, tg, sig22, f22, accB2);
             REDUCE();
             const R sb2 = (R)a.scl_b2;
 #pragma unroll
@@ -858,7 +931,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
 // Layer-boundary forward pass on tile t: the group's rotations with layer l's
 // angle (arrangements A, B, C), layer l+1's phase (in C), the same group's
 // rotations with layer l+1's angle (C, B, A); loaded and stored in A.
-template <typename R, bool TM, bool TM2>
+template <typename R, bool TM, bool TM2, int SP = -1>
 __device__ __forceinline__ void tile_pass_fwd_fuse(const PassArgs &a, uint64_t t, typename Tr<R>::V *lds)
 {
     using V = typename Tr<R>::V;
@@ -871,7 +944,7 @@ __device__ __forceinline__ void tile_pass_fwd_fuse(const PassArgs &a, uint64_t t
     const uint64_t base = tile_base(t, g);
     const bool full = g.tbits == (uint32_t)Tr<R>::TB;
     const uint32_t lim = 1u << g.tbits;
-    const uint32_t tmask = g.tmask;
+    const Targets<SP> tg{g.tmask};
     const bool strm = (a.flags & kStream) != 0;
     V *psi = (V *)a.psi;
     const CT *cost = (const CT *)a.cost;
@@ -889,23 +962,24 @@ __device__ __forceinline__ void tile_pass_fwd_fuse(const PassArgs &a, uint64_t t
     for (int r = 0; r < NR; ++r)
         v[r] = (full || elem<0, WB>(lane, wave, r) < lim) ? ld(&psi[thrA | offA(r)], strm) : zero;
     const R m1 = (R)a.mul_f, m2 = (R)a.mul_f2;
-    mix_stage<0, TM>(v, m1, tmask);
+    mix_stage<0, TM, true>(v, m1, tg);
     xpose<0, 1>(v, lds, lane, wave);
-    mix_stage<1, TM>(v, m1, tmask);
+    mix_stage<1, TM, true>(v, m1, tg);
     xpose<1, 2>(v, lds, lane, wave);
-    mix_stage<2, TM>(v, m1, tmask);
+    mix_stage<2, TM, true>(v, m1, tg);
     const R s1 = (R)a.scl_f;
+    const auto PK = phase_consts<R>();
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         R c, s;
-        phase_cs(-a.gamma_in, cv[r], c, s);
+        phase_cs(-a.gamma_in, cv[r], c, s, PK);
         v[r] = cmul(vscale(v[r], s1), c, s);
     }
-    mix_stage<2, TM2>(v, m2, tmask);
+    mix_stage<2, TM2, true>(v, m2, tg);
     xpose<2, 1>(v, lds, lane, wave);
-    mix_stage<1, TM2>(v, m2, tmask);
+    mix_stage<1, TM2, true>(v, m2, tg);
     xpose<1, 0>(v, lds, lane, wave);
-    mix_stage<0, TM2>(v, m2, tmask);
+    mix_stage<0, TM2, true>(v, m2, tg);
     const R s2 = (R)a.scl_f2;
     uint64_t thrS = thrA;  // see tile_pass_bwd_fuse
     asm volatile("" : "+v"(thrS));

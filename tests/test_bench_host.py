@@ -11,12 +11,17 @@ def test_pass_byte_model_values():
 
 
 def test_batch_byte_model_counts_sweeps():
-    # n <= 12: one sweep per layer; p = 4: forward 24 + 3 x 40, E/lam sweep 40,
-    # backward 40 + 3 x 72
-    assert bench.batch_bytes_per_amp(12, 4) == 24 + 3 * 40 + 40 + 40 + 3 * 72
-    # two sweeps per layer with boundary sweeps: forward 24 + 3 x 40 + 1 x 32,
-    # E/lam 40, backward 40 + 3 x 72 + 1 x 64
-    assert bench.batch_bytes_per_amp(20, 4) == 24 + 3 * 40 + 32 + 40 + 40 + 3 * 72 + 64
+    # n <= 12: one sweep per layer; p = 4: forward 24 + 2 x 40 (layers 0..2), the
+    # turn 40 (layer 3), backward 2 x 72 + 40 (layers 2..0)
+    assert bench.batch_bytes_per_amp(12, 4) == 24 + 2 * 40 + 40 + 2 * 72 + 40
+    # p = 1 at n <= 12: the turn generates the state and stores nothing, reading C only
+    assert bench.batch_bytes_per_amp(12, 1) == 8
+    # two sweeps per layer with boundary sweeps: forward 24 + 3 x 40, the turn 40,
+    # backward 3 x 72 + 40 (the alternating group order leaves no plain sweep)
+    assert bench.batch_bytes_per_amp(20, 4) == 24 + 3 * 40 + 40 + 3 * 72 + 40
+    # three sweeps per layer (depth 4 at n = 20): one plain sweep per layer beyond
+    # the boundary ones, each way: forward 24 + 3 x 40 + 4 x 32, backward + 4 x 64
+    assert bench.batch_bytes_per_amp(20, 4, 4) == 24 + 3 * 40 + 4 * 32 + 40 + 3 * 72 + 40 + 4 * 64
 
 
 def test_gpu_count_guard(capsys):
