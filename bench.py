@@ -35,12 +35,13 @@ HBM_PEAK_GBS = 8000.0
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_pass_traffic_qubo32_p3_c128.md")
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2407_13012_amd", "csrc", f)
-                   for f in ("kernels.hip", "tile_device.h", "plan.cpp", "api.cpp", "qaoa_internal.h")]
+                   for f in ("kernels.hip", "passes.hip", "tile_device.h", "plan.cpp", "api.cpp", "qaoa_internal.h")]
 
 
-# template instance that runs each pass kind
-KERNEL_OF = {"forward": "k_pass<{}, kFwd>", "turn": "k_pass<{}, kTurn>", "backward": "k_pass<{}, kBwd>",
-             "boundary_forward": "k_pass_fuse<{}, kFwdFuse>", "boundary_backward": "k_pass_fuse<{}, kBwdFuse>"}
+# template instance that runs each pass kind (passes.hip; one instance per
+# spectator class S of the pass, S = 0 for a layer's first group)
+KERNEL_OF = {"forward": "k_pass<{}, kFwd, S>", "turn": "k_pass<{}, kTurn, S>", "backward": "k_pass<{}, kBwd, S>",
+             "boundary_forward": "k_pass_fuse<{}, kFwdFuse, S>", "boundary_backward": "k_pass_fuse<{}, kBwdFuse, S>"}
 
 
 def kernel_source_hash() -> str:

@@ -167,6 +167,23 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
                           double *E, double *dgamma, double *dbeta);
 
 /*
+ * The gradient at the angles of the handle's current state, by the adjoint
+ * reverse sweep alone (Sec. II-B, IV-C): for a caller that has already run the
+ * forward evolution with qaoa_evaluate or qaoa_statevector at the same
+ * (gamma, beta) (an autograd forward that may or may not be followed by a
+ * backward).  The first backward pass forms lam = C phi from the stored final
+ * state; the layer states are recomputed by inverse layers as in
+ * qaoa_gradient, whose results it matches to rounding.
+ *   gamma, beta    host fp64 [p], equal (bit for bit) to the angles of the
+ *                  current state
+ *   dgamma, dbeta  host fp64 [p]
+ * Errors: NO_STATE without a current state or with a state computed at other
+ * angles.  Allocates the adjoint vector on first use.  Consumes the state.
+ */
+qaoa_status qaoa_gradient_from_state(qaoa_handle h, int32_t p, const double *gamma, const double *beta,
+                                     double *dgamma, double *dbeta);
+
+/*
  * qaoa_gradient without any device allocation, for callers that cannot
  * allocate: code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  Same results as qaoa_gradient (the same kernels in the

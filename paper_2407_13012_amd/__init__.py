@@ -39,6 +39,7 @@ from ._binding import (  # noqa: F401
     qaoa_cost_diagonal,
     qaoa_cost_extrema,
     qaoa_gradient_noalloc,
+    qaoa_gradient_from_state,
     qaoa_create_maxcut,
     qaoa_create_poly,
     qaoa_create_qubo,

@@ -91,6 +91,7 @@ def load_library() -> ctypes.CDLL:
         "qaoa_expectation": [vp, pd],
         "qaoa_evaluate": [vp, i32, vp, vp, pd],
         "qaoa_gradient": [vp, i32, vp, vp, pd, vp, vp],
+        "qaoa_gradient_from_state": [vp, i32, vp, vp, vp, vp],
         "qaoa_gradient_noalloc": [vp, i32, vp, vp, vp, vp, vp, i32],
         "qaoa_sample": [vp, i64, u64, vp, vp, i32],
         "qaoa_pass_plan": [i32, i32, i32, pi32, vp, vp],
@@ -273,6 +274,17 @@ def qaoa_gradient(h, gamma, beta):
     _check(load_library().qaoa_gradient(h, g.size, _ptr(g), _ptr(b), ctypes.byref(E), _ptr(dg), _ptr(db)),
            "qaoa_gradient")
     return E.value, dg, db
+
+
+def qaoa_gradient_from_state(h, gamma, beta):
+    """(dE/dgamma, dE/dbeta) by the reverse sweep alone, from the state that a
+    preceding qaoa_evaluate / qaoa_statevector left at the same angles."""
+    g, b = _angles(gamma, beta)
+    dg = np.zeros(g.size)
+    db = np.zeros(g.size)
+    _check(load_library().qaoa_gradient_from_state(h, g.size, _ptr(g), _ptr(b), _ptr(dg), _ptr(db)),
+           "qaoa_gradient_from_state")
+    return dg, db
 
 
 def qaoa_gradient_noalloc(h, gamma, beta, out=None):
@@ -651,6 +663,9 @@ class QaoaHandle:
 
     def gradient(self, gamma, beta):
         return qaoa_gradient(self._h, gamma, beta)
+
+    def gradient_from_state(self, gamma, beta):
+        return qaoa_gradient_from_state(self._h, gamma, beta)
 
     def gradient_noalloc(self, gamma, beta, out=None):
         return qaoa_gradient_noalloc(self._h, gamma, beta, out)

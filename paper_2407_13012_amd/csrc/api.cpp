@@ -55,6 +55,7 @@ struct qaoa_handle_s {
     size_t res_cap = 0;    // doubles
     std::vector<qk::PassPlan> plan;  // mixer sweeps of one layer (fixed by n and precision)
     bool state_valid = false;
+    std::vector<double> state_angles;  // (gamma, beta) of the current state
     bool poisoned = false;
     bool extrema_valid = false;
     double cmin = 0, cmax = 0;
@@ -381,23 +382,75 @@ qaoa_status run_forward(qaoa_handle h, int p, const double *gamma, const double 
     return QAOA_OK;
 }
 
+// Partial-sum slots of a gradient: (2p + 1) x nblocks doubles, slot 0 E,
+// slots 1 .. p the <lam|X|phi> terms of layers 0 .. p-1, slots p+1 .. 2p their
+// <lam|C|phi> terms.
+struct Slots {
+    double *parts;
+    uint64_t T;
+    int p;
+    double *E() const { return parts; }
+    double *B(int l) const { return parts + (uint64_t)(1 + l) * T; }
+    double *G(int l) const { return parts + (uint64_t)(1 + p + l) * T; }
+};
+
+// Backward sweep after the last group of layer p-1 has been undone (by the
+// turn pass or by the first pass of a reverse sweep from a stored state): each
+// layer undoes its groups in the reverse of the forward order; a layer's first
+// group also undoes its phase and, for P >= 2 and l > 0, shares its sweep with
+// the last group of layer l - 1.  Partials of <lam|X|phi>: with P >= 2 a
+// layer's slot has already been written when its own passes run (by the pass
+// that undid layer p-1's last group, or by the layer-boundary sweep of layer
+// l+1), so they add to it, and a layer-boundary sweep is always the first to
+// touch layer l-1's slot, so it overwrites it; with P = 1 every layer but the
+// last has one pass, which overwrites.
+qaoa_status enqueue_backward(qaoa_handle h, int p, const double *gamma, const double *beta, void *lam,
+                             const Slots &sl)
+{
+    const std::vector<qk::PassPlan> &G = h->plan;
+    const int P = (int)G.size();
+    for (int l = p - 1; l >= 0; --l) {
+        for (int j = 0; j < P; ++j) {
+            const int idx = P - 1 - j;
+            if (j == 0 && (l == p - 1 || P > 1)) continue;  // undone already, or fused into layer l+1
+            const int gi = P > 1 ? group_at(l, idx, P) : 0;
+            qk::PassArgs a = pass_args(h, G[gi], beta[l]);
+            a.lam = lam;
+            a.part_b = sl.B(l);
+            if (P > 1) a.flags |= qk::kBetaAcc;
+            int mode = qk::kBwd;
+            if (idx == 0) {
+                a.gamma_out = gamma[l];
+                a.part_g = sl.G(l);
+                if (P > 1 && l > 0) {
+                    mode = qk::kBwdFuse;
+                    set_second(a, beta[l - 1]);
+                    a.part_b2 = sl.B(l - 1);
+                } else {
+                    a.flags |= qk::kPhaseOut;
+                    if (l == 0) a.flags |= qk::kNoStore;
+                }
+            }
+            qaoa_status st = run_pass(h, mode, a);
+            if (st != QAOA_OK) return st;
+        }
+    }
+    return QAOA_OK;
+}
+
 // Launch sequence of the expectation and its adjoint gradient (Sec. II-B,
 // IV-C) on the handle's stream: forward sweeps, the turn sweep, backward
-// sweeps.  `lam` is the adjoint vector (2^n amplitudes) and `parts` holds
-// (2p + 1) x nblocks partial sums: slot 0 E, slots 1 .. p the <lam|X|phi>
-// terms of layers 0 .. p-1, slots p+1 .. 2p their <lam|C|phi> terms.  Every
-// slot is overwritten before it is added to, so neither buffer needs clearing.
-// Only enqueues kernels (p >= 1); allocates nothing.
+// sweeps.  `lam` is the adjoint vector (2^n amplitudes) and `parts` holds the
+// (2p + 1) x nblocks partial sums (Slots).  Every slot is overwritten before it
+// is added to, so neither buffer needs clearing.  Only enqueues kernels
+// (p >= 1); allocates nothing.
 qaoa_status enqueue_gradient(qaoa_handle h, int p, const double *gamma, const double *beta, void *lam,
                              double *parts)
 {
     qaoa_status st;
-    const uint64_t T = nblocks(h);
+    const Slots sl{parts, nblocks(h), p};
     const std::vector<qk::PassPlan> &G = h->plan;
     const int P = (int)G.size();
-    double *slotE = parts;
-    auto slotB = [&](int l) { return parts + (uint64_t)(1 + l) * T; };
-    auto slotG = [&](int l) { return parts + (uint64_t)(1 + p + l) * T; };
 
     // Forward through every group except the last group of the last layer.
     if ((st = run_forward(h, p, gamma, beta, true, false)) != QAOA_OK) return st;
@@ -407,49 +460,69 @@ qaoa_status enqueue_gradient(qaoa_handle h, int p, const double *gamma, const do
         const int l = p - 1;
         qk::PassArgs a = pass_args(h, G[P > 1 ? group_at(l, P - 1, P) : 0], beta[l]);
         a.lam = lam;
-        a.part_e = slotE;
-        a.part_b = slotB(l);
+        a.part_e = sl.E();
+        a.part_b = sl.B(l);
         if (P == 1) {
             a.flags |= qk::kPhaseIn | qk::kPhaseOut;
             a.gamma_in = a.gamma_out = gamma[l];
-            a.part_g = slotG(l);
+            a.part_g = sl.G(l);
             if (l == 0) a.flags |= qk::kInit | qk::kNoStore;
         }
         if ((st = run_pass(h, P == 1 ? qk::kTurnPhase : qk::kTurn, a)) != QAOA_OK) return st;
     }
-    // Backward sweep: each layer undoes its groups in the reverse of the forward
-    // order; a layer's first group also undoes its phase and, for P >= 2 and
-    // l > 0, shares its sweep with the last group of layer l - 1.  Partials of
-    // <lam|X|phi>: with P >= 2 a layer's slot has already been written when its
-    // own passes run (by the turn pass for layer p-1, by the layer-boundary
-    // sweep of layer l+1 otherwise), so they add to it, and a layer-boundary
-    // sweep is always the first to touch layer l-1's slot, so it overwrites it;
-    // with P = 1 every layer but the last has one pass, which overwrites.
-    for (int l = p - 1; l >= 0; --l) {
-        for (int j = 0; j < P; ++j) {
-            const int idx = P - 1 - j;
-            if (j == 0 && (l == p - 1 || P > 1)) continue;  // turn pass, or fused into layer l+1
-            const int gi = P > 1 ? group_at(l, idx, P) : 0;
-            qk::PassArgs a = pass_args(h, G[gi], beta[l]);
-            a.lam = lam;
-            a.part_b = slotB(l);
-            if (P > 1) a.flags |= qk::kBetaAcc;
-            int mode = qk::kBwd;
-            if (idx == 0) {
-                a.gamma_out = gamma[l];
-                a.part_g = slotG(l);
-                if (P > 1 && l > 0) {
-                    mode = qk::kBwdFuse;
-                    set_second(a, beta[l - 1]);
-                    a.part_b2 = slotB(l - 1);
-                } else {
-                    a.flags |= qk::kPhaseOut;
-                    if (l == 0) a.flags |= qk::kNoStore;
-                }
-            }
-            if ((st = run_pass(h, mode, a)) != QAOA_OK) return st;
-        }
+    return enqueue_backward(h, p, gamma, beta, lam, sl);
+}
+
+// Reverse sweep from the final state phi(gamma, beta) held in psi: the first
+// backward pass forms lam = C phi as it loads phi, undoes the last group of
+// layer p-1 on both vectors with its <lam|X|phi> terms (and, with one group
+// per layer, the phase with the <lam|C|phi> term) and stores both; the rest is
+// the gradient's backward sweep.  Slot 0 (E) is not written.
+qaoa_status enqueue_reverse(qaoa_handle h, int p, const double *gamma, const double *beta, void *lam,
+                            double *parts)
+{
+    const Slots sl{parts, nblocks(h), p};
+    const std::vector<qk::PassPlan> &G = h->plan;
+    const int P = (int)G.size();
+    const int l = p - 1;
+    qk::PassArgs a = pass_args(h, G[P > 1 ? group_at(l, P - 1, P) : 0], beta[l]);
+    a.lam = lam;
+    a.part_b = sl.B(l);
+    a.flags |= qk::kLamFromC;
+    if (P == 1) {
+        a.flags |= qk::kPhaseOut;
+        a.gamma_out = gamma[l];
+        a.part_g = sl.G(l);
+        if (l == 0) a.flags |= qk::kNoStore;
     }
+    qaoa_status st = run_pass(h, qk::kBwd, a);
+    if (st != QAOA_OK) return st;
+    return enqueue_backward(h, p, gamma, beta, lam, sl);
+}
+
+// Records the angles of the state just computed (qaoa_gradient_from_state
+// checks them).
+qaoa_status keep_angles(qaoa_handle h, int p, const double *gamma, const double *beta)
+{
+    try {
+        h->state_angles.assign(gamma, gamma + p);
+        h->state_angles.insert(h->state_angles.end(), beta, beta + p);
+    } catch (...) {
+        return fail(QAOA_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+    return QAOA_OK;
+}
+
+// Adjoint vector of the handle, allocated on first use.
+qaoa_status ensure_lam(qaoa_handle h)
+{
+    if (h->lam) return QAOA_OK;
+    size_t fr = 0, tot = 0;
+    HIPCHECK(h, hipMemGetInfo(&fr, &tot));
+    if (!fits(h, (double)h->N * amp_bytes(h->prec), fr))
+        return fail(QAOA_ERR_OUT_OF_MEMORY, "adjoint vector does not fit in free device memory");
+    if (dev_alloc(h, &h->lam, h->N * amp_bytes(h->prec)) != hipSuccess)
+        return fail(QAOA_ERR_OUT_OF_MEMORY, "adjoint vector allocation failed");
     return QAOA_OK;
 }
 
@@ -817,6 +890,7 @@ qaoa_status qaoa_statevector(qaoa_handle h, int32_t p, const double *gamma, cons
     } else if ((st = run_forward(h, p, gamma, beta, false, false)) != QAOA_OK) {
         return st;
     }
+    if ((st = keep_angles(h, p, gamma, beta)) != QAOA_OK) return st;
     h->state_valid = true;
     if (out) {
         HIPCHECK(h, hipMemcpyAsync(out, h->psi, h->N * amp_bytes(h->prec),
@@ -856,6 +930,7 @@ qaoa_status qaoa_evaluate(qaoa_handle h, int32_t p, const double *gamma, const d
     const uint64_t T = nblocks(h);
     if ((st = ensure_doubles(h, &h->parts, &h->parts_cap, T)) != QAOA_OK) return st;
     if ((st = run_forward(h, p, gamma, beta, false, true)) != QAOA_OK) return st;
+    if ((st = keep_angles(h, p, gamma, beta)) != QAOA_OK) return st;
     h->state_valid = true;
     return fetch_results(h, 1, T, E);
 }
@@ -875,14 +950,7 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
         return QAOA_OK;
     }
     DeviceGuard dg(h->device);
-    if (!h->lam) {
-        size_t fr = 0, tot = 0;
-        HIPCHECK(h, hipMemGetInfo(&fr, &tot));
-        if (!fits(h, (double)h->N * amp_bytes(h->prec), fr))
-            return fail(QAOA_ERR_OUT_OF_MEMORY, "adjoint vector does not fit in free device memory");
-        if (dev_alloc(h, &h->lam, h->N * amp_bytes(h->prec)) != hipSuccess)
-            return fail(QAOA_ERR_OUT_OF_MEMORY, "adjoint vector allocation failed");
-    }
+    if ((st = ensure_lam(h)) != QAOA_OK) return st;
     const uint64_t T = nblocks(h);
     const int nslots = 2 * p + 1;
     if ((st = ensure_doubles(h, &h->parts, &h->parts_cap, (size_t)nslots * T)) != QAOA_OK) return st;
@@ -896,6 +964,40 @@ qaoa_status qaoa_gradient(qaoa_handle h, int32_t p, const double *gamma, const d
     for (int l = 0; l < p; ++l) {
         dbeta[l] = 2.0 * r[1 + l];
         dgamma[l] = 2.0 * r[1 + p + l];
+    }
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_gradient_from_state(qaoa_handle h, int32_t p, const double *gamma, const double *beta,
+                                     double *dgamma, double *dbeta)
+{
+    qaoa_status st = check_handle(h);
+    if (st != QAOA_OK) return st;
+    if ((st = check_angles(p, gamma, beta)) != QAOA_OK) return st;
+    if (p > 0 && (!dgamma || !dbeta)) return fail(QAOA_ERR_INVALID_ARGUMENT, "gradient output is NULL");
+    if (!h->state_valid) return fail(QAOA_ERR_NO_STATE, "no current state (run qaoa_evaluate or qaoa_statevector first)");
+    bool same = h->state_angles.size() == (size_t)(2 * p);
+    for (int l = 0; same && l < p; ++l)
+        same = h->state_angles[l] == gamma[l] && h->state_angles[p + l] == beta[l];
+    if (!same) return fail(QAOA_ERR_NO_STATE, "the current state was computed at other angles");
+    if (p == 0) return QAOA_OK;
+    DeviceGuard dg(h->device);
+    if ((st = ensure_lam(h)) != QAOA_OK) return st;
+    const uint64_t T = nblocks(h);
+    const int nslots = 2 * p + 1;
+    if ((st = ensure_doubles(h, &h->parts, &h->parts_cap, (size_t)nslots * T)) != QAOA_OK) return st;
+    if ((st = ensure_doubles(h, &h->res, &h->res_cap, (size_t)nslots)) != QAOA_OK) return st;
+    h->state_valid = false;
+    if ((st = enqueue_reverse(h, p, gamma, beta, h->lam, h->parts)) != QAOA_OK) return st;
+    // slots 1 .. 2p (slot 0, E, is not written by the reverse sweep)
+    HIPCHECK(h, qk::launch_sum_slots(h->parts + T, T, T, 2 * p, h->res, h->stream));
+    std::vector<double> r((size_t)(2 * p));
+    HIPCHECK(h, hipMemcpyAsync(r.data(), h->res, (size_t)(2 * p) * sizeof(double), hipMemcpyDeviceToHost,
+                               h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    for (int l = 0; l < p; ++l) {
+        dbeta[l] = 2.0 * r[l];
+        dgamma[l] = 2.0 * r[p + l];
     }
     return QAOA_OK;
 }

@@ -42,7 +42,8 @@ enum PassFlags : int {
     kNoStore = 16,   // skip the final store (last backward pass)
     kBetaAcc = 32,   // add the <lam|X|phi> partial to the existing one instead of overwriting
     kStream = 64,    // nontemporal loads/stores (tiles with long contiguous runs)
-    kBetaAcc2 = 128  // kBetaAcc for the second rotation's partials (kBwdFuse)
+    kBetaAcc2 = 128, // kBetaAcc for the second rotation's partials (kBwdFuse)
+    kLamFromC = 256  // (kBwd) lam = C phi formed from the loaded phi instead of loaded
 };
 
 // One pass of a mixer layer.  A tile is the set of 2^TB basis indices that

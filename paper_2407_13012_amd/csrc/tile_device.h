@@ -687,6 +687,10 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
     // All global loads of the pass are issued up front (cost entries first);
     // loads placed after the arithmetic were found to serialise with it.
     constexpr bool TURN = MODE == kTurn || MODE == kTurnPhase;
+    // complex128 passes whose B arrangement holds no target bit (S >= 4 spectator
+    // bits, all of B's register bits) go from A to C and back with one transpose
+    // (not the turn, which re-reads its tile from B's transpose)
+    constexpr bool kSkipB = SP >= 4 && WB == 2 && !TURN;
     // which optional steps this launch performs (compile-time where the mode decides)
     const bool phaseIn = MODE == kTurnPhase || (MODE == kFwd && (a.flags & kPhaseIn));
     const bool phaseOut = MODE == kTurnPhase || MODE == kBwdFuse || (MODE == kBwd && (a.flags & kPhaseOut));
@@ -740,9 +744,13 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
         }
         const R mf = (R)a.mul_f;
         mix_stage<0, TM, !TURN>(v, mf, tg);
-        xpose<0, 1>(v, lds, lane, wave);
-        mix_stage<1, TM, !TURN>(v, mf, tg);
-        xpose<1, 2>(v, lds, lane, wave);
+        if constexpr (kSkipB) {
+            xpose<0, 2>(v, lds, lane, wave);
+        } else {
+            xpose<0, 1>(v, lds, lane, wave);
+            mix_stage<1, TM, !TURN>(v, mf, tg);
+            xpose<1, 2>(v, lds, lane, wave);
+        }
         mix_stage<2, TM, !TURN>(v, mf, tg);
         const R sf = (R)a.scl_f;
 #pragma unroll
@@ -846,22 +854,38 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
         }
     } else {
         V f[NR], l[NR];
+        if (MODE == kBwd && (a.flags & kLamFromC)) {
+            // the first pass of a reverse sweep from a stored final state: lam = C phi
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const bool ok = VA(r);
-            f[r] = ok ? ld(&psi[ZA(r)], strm) : zero;
-            l[r] = ok ? ld(&lam[ZA(r)], strm) : zero;
+            for (int r = 0; r < NR; ++r) {
+                const bool ok = VA(r);
+                const CT c = ok ? ld(&cost[ZA(r)], strm) : (CT)0;
+                f[r] = ok ? ld(&psi[ZA(r)], strm) : zero;
+                l[r] = vscale(f[r], (R)c);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const bool ok = VA(r);
+                f[r] = ok ? ld(&psi[ZA(r)], strm) : zero;
+                l[r] = ok ? ld(&lam[ZA(r)], strm) : zero;
+            }
         }
         if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
         const R mb = (R)a.mul_b;
         const double f2 = a.fac_b * a.fac_b;
         double sig2 = 1.0;
         adj_stage<0, TM>(f, l, mb, tg, sig2, f2, accB);
-        xpose<0, 1>(f, lds, lane, wave);
-        xpose<0, 1>(l, lds, lane, wave);
-        adj_stage<1, TM>(f, l, mb, tg, sig2, f2, accB);
-        xpose<1, 2>(f, lds, lane, wave);
-        xpose<1, 2>(l, lds, lane, wave);
+        if constexpr (kSkipB) {
+            xpose<0, 2>(f, lds, lane, wave);
+            xpose<0, 2>(l, lds, lane, wave);
+        } else {
+            xpose<0, 1>(f, lds, lane, wave);
+            xpose<0, 1>(l, lds, lane, wave);
+            adj_stage<1, TM>(f, l, mb, tg, sig2, f2, accB);
+            xpose<1, 2>(f, lds, lane, wave);
+            xpose<1, 2>(l, lds, lane, wave);
+        }
         adj_stage<2, TM>(f, l, mb, tg, sig2, f2, accB);
         const R sb = (R)a.scl_b;
 #pragma unroll
@@ -895,11 +919,16 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
             const double f22 = a.fac_b2 * a.fac_b2;
             double sig22 = 1.0;
             adj_stage<2, TM2>(f, l, mb2, tg, sig22, f22, accB2);
-            xpose<2, 1>(f, lds, lane, wave);
-            xpose<2, 1>(l, lds, lane, wave);
-            adj_stage<1, TM2>(f, l, mb2, tg, sig22, f22, accB2);
-            xpose<1, 0>(f, lds, lane, wave);
-            xpose<1, 0>(l, lds, lane, wave);
+            if constexpr (kSkipB) {
+                xpose<2, 0>(f, lds, lane, wave);
+                xpose<2, 0>(l, lds, lane, wave);
+            } else {
+                xpose<2, 1>(f, lds, lane, wave);
+                xpose<2, 1>(l, lds, lane, wave);
+                adj_stage<1, TM2>(f, l, mb2, tg, sig22, f22, accB2);
+                xpose<1, 0>(f, lds, lane, wave);
+                xpose<1, 0>(l, lds, lane, wave);
+            }
             adj_stage<0, TM2>(f, l, mb2, tg, sig22, f22, accB2);
             REDUCE();
             const R sb2 = (R)a.scl_b2;
@@ -962,10 +991,17 @@ __device__ __forceinline__ void tile_pass_fwd_fuse(const PassArgs &a, uint64_t t
     for (int r = 0; r < NR; ++r)
         v[r] = (full || elem<0, WB>(lane, wave, r) < lim) ? ld(&psi[thrA | offA(r)], strm) : zero;
     const R m1 = (R)a.mul_f, m2 = (R)a.mul_f2;
+    // complex128 passes whose B arrangement holds no target bit go from A to C
+    // (and back) with one transpose
+    constexpr bool kSkipB = SP >= 4 && WB == 2;
     mix_stage<0, TM, true>(v, m1, tg);
-    xpose<0, 1>(v, lds, lane, wave);
-    mix_stage<1, TM, true>(v, m1, tg);
-    xpose<1, 2>(v, lds, lane, wave);
+    if constexpr (kSkipB) {
+        xpose<0, 2>(v, lds, lane, wave);
+    } else {
+        xpose<0, 1>(v, lds, lane, wave);
+        mix_stage<1, TM, true>(v, m1, tg);
+        xpose<1, 2>(v, lds, lane, wave);
+    }
     mix_stage<2, TM, true>(v, m1, tg);
     const R s1 = (R)a.scl_f;
     const auto PK = phase_consts<R>();
@@ -976,9 +1012,13 @@ __device__ __forceinline__ void tile_pass_fwd_fuse(const PassArgs &a, uint64_t t
         v[r] = cmul(vscale(v[r], s1), c, s);
     }
     mix_stage<2, TM2, true>(v, m2, tg);
-    xpose<2, 1>(v, lds, lane, wave);
-    mix_stage<1, TM2, true>(v, m2, tg);
-    xpose<1, 0>(v, lds, lane, wave);
+    if constexpr (kSkipB) {
+        xpose<2, 0>(v, lds, lane, wave);
+    } else {
+        xpose<2, 1>(v, lds, lane, wave);
+        mix_stage<1, TM2, true>(v, m2, tg);
+        xpose<1, 0>(v, lds, lane, wave);
+    }
     mix_stage<0, TM2, true>(v, m2, tg);
     const R s2 = (R)a.scl_f2;
     uint64_t thrS = thrA;  // see tile_pass_bwd_fuse
