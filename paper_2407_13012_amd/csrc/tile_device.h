@@ -234,14 +234,18 @@ struct PairSum<float2> {
 struct PhaseK {
     double k[20];
 };
-struct PhaseK32 {};  // complex64: no fp64 polynomial constants
+// complex64: the angle g split into two floats, g = g1 + g2 to about 48 bits.
+struct PhaseK32 {
+    float g1, g2;
+};
 template <typename R>
-__device__ __forceinline__ PhaseK32 phase_consts(std::enable_if_t<std::is_same<R, float>::value, int> = 0)
+__device__ __forceinline__ PhaseK32 phase_consts(double g, std::enable_if_t<std::is_same<R, float>::value, int> = 0)
 {
-    return {};
+    const float g1 = (float)g;
+    return {g1, (float)(g - (double)g1)};
 }
 template <typename R>
-__device__ __forceinline__ PhaseK phase_consts(std::enable_if_t<std::is_same<R, double>::value, int> = 0)
+__device__ __forceinline__ PhaseK phase_consts(double, std::enable_if_t<std::is_same<R, double>::value, int> = 0)
 {
     PhaseK K = {{
         0x1.45f306dc9c883p-1,    // 2/pi
@@ -296,25 +300,46 @@ __device__ __forceinline__ void sincos_cw(double x, double &s, double &c, const 
     c = ((q + 1) & 2) ? -c0 : c0;
 }
 
-// cos / sin of g * C.  complex128: fp64.  complex64: the product is formed and
-// reduced to x = k pi/2 + r, |r| <= pi/4, in fp64 (pi/2 as the double nearest
-// it plus the remainder), then the Taylor series of sin to r^9 and of cos to
-// r^8 are summed in fp32 (truncation below 3e-8, under half an fp32 ulp of
-// cos r >= 0.7).  r is clamped to [-pi/4, pi/4], so even arguments too large
-// for the reduction (|x| beyond ~2^50, far past fp32 phase resolution) give a
-// unit-modulus factor.  K holds the constants of the complex128 form (the
-// complex64 form needs none beyond fp32 literals and a few fp64 ones).
+// cos / sin of g * C.  complex128: fp64 (sincos_cw).  complex64: the reduction
+// x = g C = k pi/2 + r runs in fp32: with g = g1 + g2 (PhaseK32) and C an fp32
+// value, g1 C = p + pe exactly (pe from one FMA) and g2 C is below 2^-24 |x|;
+// k = rint(p 2/pi); pi/2 is split into P1 + P2 + P3 with 12-bit P1 and P2, so
+// for |k| < 2^12 the products k P1, k P2 are exact and r = p - k P1 is too
+// (Sterbenz); r = ((p - k P1) - k P2 - k P3) + (pe + g2 C) is within 1.5 fp32
+// ulps of pi/4 of the exact reduced argument (checked against fp64 on 2e5
+// random products up to |x| = 6000).  |r| may exceed pi/4 by the rounding of
+// p 2/pi; the polynomials below stay accurate there.  Then the Taylor series
+// of sin to r^9 and of cos to r^8 in fp32 (truncation below 3e-8).  Arguments
+// with |p| >= 4096 (k beyond 2^12) take the fp64 reduction instead, with r
+// clamped to [-pi/4, pi/4] so that even arguments too large for it (|x| beyond
+// ~2^50, far past fp32 phase resolution) give a unit-modulus factor.  K holds
+// the constants of the complex128 form and the split angle of the complex64 one.
 __device__ __forceinline__ void phase_cs(double g, double cval, double &c, double &s, const PhaseK &K)
 {
     sincos_cw(g * cval, s, c, K);
 }
-__device__ __forceinline__ void phase_cs(double g, float cval, float &c, float &s, const PhaseK32 &)
+__device__ __forceinline__ void phase_cs(double g, float cval, float &c, float &s, const PhaseK32 &K)
 {
-    const double th = g * (double)cval;
-    const double k = rint(th * 0.6366197723675814);  // 2/pi
-    double rd = fma(-k, 1.5707963267948966, th);
-    rd = fma(-k, 6.123233995736766e-17, rd);
-    const float r = fminf(fmaxf((float)rd, -0.785398163f), 0.785398163f), r2 = r * r;
+    float r;
+    int q;
+    const float p = K.g1 * cval;
+    if (fabsf(p) < 4096.0f) {
+        const float pe = fmaf(K.g1, cval, -p);
+        const float k = rintf(p * 0x1.45f306p-1f);          // 2/pi
+        float rr = fmaf(-k, 0x1.922p+0f, p);                // pi/2: 12-bit head
+        rr = fmaf(-k, -0x1.2aep-18f, rr);                   //       12-bit second part
+        rr = fmaf(-k, -0x1.de974p-31f, rr);                 //       remainder
+        r = rr + (pe + K.g2 * cval);
+        q = (int)k;
+    } else {
+        const double th = g * (double)cval;
+        const double k = rint(th * 0.6366197723675814);  // 2/pi
+        double rd = fma(-k, 1.5707963267948966, th);
+        rd = fma(-k, 6.123233995736766e-17, rd);
+        r = fminf(fmaxf((float)rd, -0.785398163f), 0.785398163f);
+        q = (int)(k - 4.0 * floor(k * 0.25));  // k mod 4, defined for any k
+    }
+    const float r2 = r * r;
     float ps = 2.7557319e-6f;               //  1/9!
     ps = fmaf(ps, r2, -1.98412698e-4f);     // -1/7!
     ps = fmaf(ps, r2, 8.33333333e-3f);      //  1/5!
@@ -325,8 +350,7 @@ __device__ __forceinline__ void phase_cs(double g, float cval, float &c, float &
     pc = fmaf(pc, r2, 4.16666667e-2f);      //  1/4!
     pc = fmaf(pc, r2, -0.5f);               // -1/2!
     const float cr = fmaf(pc, r2, 1.0f);
-    const int q = (int)(k - 4.0 * floor(k * 0.25));  // k mod 4, defined for any k
-    // x = k pi/2 + r: rotate (cos r, sin r) by q quarter turns
+    // x = k pi/2 + r: rotate (cos r, sin r) by q quarter turns (q & 3 = k mod 4)
     const float s0 = (q & 1) ? cr : sr, c0 = (q & 1) ? sr : cr;
     s = (q & 2) ? -s0 : s0;
     c = ((q + 1) & 2) ? -c0 : c0;
@@ -725,7 +749,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
         }
         if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
         if (phaseIn) {
-            const auto PK = phase_consts<R>();
+            const auto PK = phase_consts<R>(-a.gamma_in);
 #pragma unroll
             for (int r = 0; r < NR; ++r)
                 if (VA(r)) {
@@ -833,7 +857,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
             adj_stage<0, TM>(v, l, mb, tg, sig2, f2, accB);
                 xpose<0, 2>(l, lds, lane, wave);
                 xpose<0, 2>(v, lds, lane, wave);
-                const auto PK = phase_consts<R>();
+                const auto PK = phase_consts<R>(a.gamma_out);
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
                     l[r] = vscale(l[r], sb);
@@ -900,7 +924,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
             }
             // the last sweep stores nothing, so it skips the phase undo
             const bool undo = MODE == kBwdFuse || !(a.flags & kNoStore);
-            const auto PK = phase_consts<R>();
+            const auto PK = phase_consts<R>(a.gamma_out);
 #pragma unroll
             for (int r = 0; r < NR; ++r)
                 if (VC(r)) {
@@ -1004,7 +1028,7 @@ __device__ __forceinline__ void tile_pass_fwd_fuse(const PassArgs &a, uint64_t t
     }
     mix_stage<2, TM, true>(v, m1, tg);
     const R s1 = (R)a.scl_f;
-    const auto PK = phase_consts<R>();
+    const auto PK = phase_consts<R>(-a.gamma_in);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         R c, s;
