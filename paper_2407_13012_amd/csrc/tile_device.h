@@ -918,24 +918,33 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
             l[r] = vscale(l[r], sb);
         }
         if (phaseOut) {
-            if constexpr (kLateCost) {
-#pragma unroll
-                for (int r = 0; r < NR; ++r) cv[r] = VC(r) ? ld(&cost[ZC(r)], strm) : (CT)0;
-            }
             // the last sweep stores nothing, so it skips the phase undo
             const bool undo = MODE == kBwdFuse || !(a.flags & kNoStore);
             const auto PK = phase_consts<R>(a.gamma_out);
+            // with late cost loads, eight entries at a time (fewer registers live)
+            constexpr int H = kLateCost ? NR / 2 : NR;
 #pragma unroll
-            for (int r = 0; r < NR; ++r)
-                if (VC(r)) {
-                    accG += (double)cv[r] * imcx(l[r], f[r]);
-                    if (undo) {
-                        R c, s;
-                        phase_cs(a.gamma_out, cv[r], c, s, PK);
-                        f[r] = cmul(f[r], c, s);
-                        l[r] = cmul(l[r], c, s);
-                    }
+            for (int h = 0; h < NR; h += H) {
+                if constexpr (kLateCost) {
+#pragma unroll
+                    for (int r = h; r < h + H; ++r) cv[r] = VC(r) ? ld(&cost[ZC(r)], strm) : (CT)0;
                 }
+#pragma unroll
+                for (int r = h; r < h + H; ++r)
+                    if (VC(r)) {
+                        accG += (double)cv[r] * imcx(l[r], f[r]);
+                        if (undo) {
+                            R c, s;
+                            phase_cs(a.gamma_out, cv[r], c, s, PK);
+                            f[r] = cmul(f[r], c, s);
+                            l[r] = cmul(l[r], c, s);
+                        }
+                    }
+                if constexpr (kLateCost) {
+                    asm volatile("" : "+v"(accG));
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
         }
         if constexpr (MODE == kBwdFuse) {
             // the same group's rotations of the previous layer, undone from C back to A
