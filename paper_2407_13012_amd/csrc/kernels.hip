@@ -412,10 +412,6 @@ int static_spectators(const Geometry &g, bool c64, int mode)
     if ((int)g.tbits != TB || t == 0) return -1;
     const int S = __builtin_ctz(t);
     if (t != (((1u << TB) - 1u) & ~((1u << S) - 1u))) return -1;  // not "every bit from S up"
-    // complex64 layer-boundary backward sweeps keep the run-time mask: with the
-    // stages fixed the compiler spills a dozen registers in them (128 allowed)
-    // and the sweep is no faster (38.2 vs 37.4 ms at n = 32)
-    if (c64 && mode == kBwdFuse) return -1;
     if (S == 0) return 0;
     return (S >= 2 && S <= 7 && mode != kTurnPhase) ? S : -1;
 }

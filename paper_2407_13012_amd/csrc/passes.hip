@@ -96,10 +96,7 @@ hipError_t launch_pass_sp(int mode, const PassArgs &a, uint64_t nblocks, hipStre
     if (mode == kFwdFuse) {
         launch_fuse<R, kFwdFuse, SP>(a, grid, s);
     } else if (mode == kBwdFuse) {
-        // complex64 layer-boundary backward sweeps run the run-time-mask kernels
-        // (static_spectators)
-        if constexpr (std::is_same<R, float>::value && SP >= 0) return hipErrorInvalidValue;
-        else launch_fuse<R, kBwdFuse, SP>(a, grid, s);
+        launch_fuse<R, kBwdFuse, SP>(a, grid, s);
     } else if (mode == kTurnPhase) {
         // the one-pass turn (n <= TB): its tile holds every qubit, no spectators
         if constexpr (SP > 0) return hipErrorInvalidValue;

@@ -926,8 +926,13 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
 #pragma unroll
             for (int h = 0; h < NR; h += H) {
                 if constexpr (kLateCost) {
+                    // addresses formed afresh from the thread index: kept from the
+                    // start of the tile they would be spilled
+                    uint32_t tid2 = threadIdx.x;
+                    asm volatile("" : "+v"(tid2));
+                    const uint64_t thrC2 = base | dep(elem<2, WB>(tid2 & 63u, tid2 >> 6, 0), g);
 #pragma unroll
-                    for (int r = h; r < h + H; ++r) cv[r] = VC(r) ? ld(&cost[ZC(r)], strm) : (CT)0;
+                    for (int r = h; r < h + H; ++r) cv[r] = VC(r) ? ld(&cost[thrC2 | offC(r)], strm) : (CT)0;
                 }
 #pragma unroll
                 for (int r = h; r < h + H; ++r)
@@ -965,11 +970,14 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
             adj_stage<0, TM2>(f, l, mb2, tg, sig22, f22, accB2);
             REDUCE();
             const R sb2 = (R)a.scl_b2;
+            uint32_t tid3 = threadIdx.x;
+            asm volatile("" : "+v"(tid3));
+            const uint64_t thrA3 = kLateCost ? (base | dep(elem<0, WB>(tid3 & 63u, tid3 >> 6, 0), g)) : thrA;
 #pragma unroll
             for (int r = 0; r < NR; ++r)
                 if (VA(r)) {
-                    st(vscale(f[r], sb2), &psi[ZA(r)], strm);
-                    st(vscale(l[r], sb2), &lam[ZA(r)], strm);
+                    st(vscale(f[r], sb2), &psi[thrA3 | offA(r)], strm);
+                    st(vscale(l[r], sb2), &lam[thrA3 | offA(r)], strm);
                 }
         } else {
             REDUCE();
