@@ -273,10 +273,21 @@ __device__ __forceinline__ PhaseK phase_consts(double, std::enable_if_t<std::is_
     for (int i = 0; i < 20; ++i) asm volatile("" : "+s"(K.k[i]));
     return K;
 }
+// Arguments beyond the reduction's range (never met by the phases of real
+// instances) go to the library's sincos, kept out of line so that the 16
+// unrolled phase evaluations of a tile do not each carry a copy of it.
+__device__ __attribute__((noinline)) double2 sincos_far(double x)
+{
+    double s, c;
+    sincos(x, &s, &c);
+    return make_double2(s, c);
+}
 __device__ __forceinline__ void sincos_cw(double x, double &s, double &c, const PhaseK &K)
 {
     if (!(fabs(x) < 1.0e6)) {
-        sincos(x, &s, &c);
+        const double2 sc = sincos_far(x);
+        s = sc.x;
+        c = sc.y;
         return;
     }
     const double k = rint(x * K.k[0]);
