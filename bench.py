@@ -195,12 +195,31 @@ def batch_leg(count: int, p: int, steps: int, log) -> dict:
         t0 = time.perf_counter()
         gam, bet, e0, e1 = b.run(g0, b0)
         dt = time.perf_counter() - t0
+        t_start, t_end, which = b.timeline()
     ns = np.array([g.n for g in graphs])
     kmax = {int(k): int(v) for k, v in choice["group_by_n"].items()}
     amps = float(np.sum(2.0 ** ns))
-    algo = sum(batch_bytes_per_amp(int(n), p, kmax.get(int(n), 10)) * 2.0 ** n for n in ns) * steps
+    res_n = opts["resident_max_n"]
+    # LDS-resident instances move only their cost entries through memory
+    algo = sum((8.0 * (2 * p - 1) if n <= res_n else batch_bytes_per_amp(int(n), p, kmax.get(int(n), 10)))
+               * 2.0 ** n for n in ns) * steps
     evals = count * steps
     log(f"[bench] batch {count} graphs x {steps} steps: {dt:.2f} s ({evals / dt:.0f} E+G/s)")
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    launches = {}
+    for k, name in ((0, "streamed"), (1, "resident")):
+        sel = which == k
+        if not np.any(sel):
+            continue
+        grid = min(opts["workgroups"], int(sel.sum())) if k == 0 else min(cus, opts["workgroups"], int(sel.sum()))
+        span = float(t_end[sel].max() - t_start[sel].min())
+        busy = float(np.sum(t_end[sel] - t_start[sel]))
+        launches[name] = {"instances": int(sel.sum()), "workgroups": grid, "span_s": span,
+                          "busy_fraction": busy / (grid * span) if span > 0 else None,
+                          "first_start_s": float(t_start[sel].min())}
+    big = ns == ns.max()
+    launches["largest_n"] = {"n": int(ns.max()), "mean_s": float(np.mean(t_end[big] - t_start[big])),
+                             "last_end_s": float(t_end[big].max())}
     return {
         "graphs": count, "p": p, "adam_steps": steps, "seconds": dt,
         "grad_evals_per_s": evals / dt,
@@ -208,8 +227,9 @@ def batch_leg(count: int, p: int, steps: int, log) -> dict:
         "algorithmic_GBps": algo / dt / 1e9,
         "mean_E_gain": float(np.mean(e1 - e0)),
         "improved_fraction": float(np.mean(e1 > e0)),
-        "tuned": {k: choice[k] for k in ("group_by_n", "waves_per_simd", "workgroups")},
+        "tuned": {k: choice[k] for k in ("group_by_n", "waves_per_simd", "workgroups", "resident_max_n")},
         "tune_s": t_tune,
+        "timeline": launches,
     }
 
 

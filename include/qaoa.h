@@ -313,6 +313,14 @@ qaoa_status qaoa_pass_plan(int32_t n, int32_t precision, int32_t cap, int32_t *n
  * theta += lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps), t = 1, 2, ...
  * The queue-reset kernel and the engine are captured once in a hipGraph and
  * replayed by every qaoa_batch_run.
+ *
+ * Instances of at most 12 qubits are a single 4096-amplitude tile.  With
+ * resident_max_n set, those up to that size run in a second persistent launch
+ * after the first, whose workgroups (one per compute unit) keep the instance's
+ * state and adjoint vector in LDS through all of its Adam steps instead of
+ * streaming them through the slot between passes; results are the same.  Each
+ * such workgroup is faster, but the streamed launch fits two per compute unit,
+ * so which mode wins depends on the batch (the autotuner measures both).
  */
 typedef struct qaoa_batch_s *qaoa_batch;
 
@@ -330,6 +338,8 @@ typedef struct {
     int32_t use_graph;  /* nonzero: replay a captured hipGraph; 0: launch eagerly */
     int32_t waves_per_simd; /* register budget of the engine kernel: 1 or 2 waves per SIMD (0 = 1) */
     int32_t group_by_n[QAOA_BATCH_MAX_QUBITS + 1]; /* per-n override of max_group; 0 = none */
+    int32_t resident_max_n; /* instances with n <= this (0..12) keep state and adjoint vector in
+                               LDS; 0 = none */
 } qaoa_batch_options;
 
 /*
@@ -340,7 +350,7 @@ typedef struct {
  *   edges         host int32 [E][2] with vertex indices local to the instance
  *                 (0 <= u, v < n[i], u != v); E = edge_offsets[count]
  *   w             host fp64 [E], finite; NULL means unit weights
- *   opt           NULL means {100, 0.05, 0.9, 0.999, 1e-8, 0, 10, 1, 0, {0}}
+ *   opt           NULL means {100, 0.05, 0.9, 0.999, 1e-8, 0, 10, 1, 0, {0}, 0}
  * Allocates all device memory (instances, angles, scratch slots) on the current
  * device and its own non-blocking stream; nothing is allocated by qaoa_batch_run.
  * Errors: INVALID_ARGUMENT, OUT_OF_MEMORY (slots exceed free memory), DEVICE.
@@ -359,6 +369,17 @@ qaoa_status qaoa_batch_create(int32_t count, const int32_t *n, const int64_t *ed
  */
 qaoa_status qaoa_batch_run(qaoa_batch b, const double *gamma0, const double *beta0, double *gamma,
                            double *beta, double *e_first, double *e_last);
+
+/*
+ * Timeline of the last qaoa_batch_run: for every instance (host fp64 [count]
+ * each, may be NULL) the time its workgroup took it from the queue and the
+ * time it wrote its results, in seconds from the earliest start, read from the
+ * device's constant-rate wall clock; which_launch (host int32 [count], may be
+ * NULL) is 0 for the streamed launch and 1 for the LDS-resident one.  For
+ * measuring how evenly the persistent workgroups are loaded.
+ * Errors: INVALID_ARGUMENT (no run yet); DEVICE.
+ */
+qaoa_status qaoa_batch_timeline(qaoa_batch b, double *start_s, double *end_s, int32_t *which_launch);
 
 /* Release the batch's device memory, graph and stream.  NULL is accepted. */
 qaoa_status qaoa_batch_destroy(qaoa_batch b);

@@ -34,6 +34,7 @@ from ._binding import (  # noqa: F401
     qaoa_batch_create,
     qaoa_batch_destroy,
     qaoa_batch_run,
+    qaoa_batch_timeline,
     library_path,
     load_library,
     qaoa_cost_diagonal,

@@ -31,7 +31,8 @@ class BatchOptions(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int32), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
                 ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("workgroups", ctypes.c_int32),
                 ("max_group", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("waves_per_simd", ctypes.c_int32), ("group_by_n", ctypes.c_int32 * (BATCH_MAX_QUBITS + 1))]
+                ("waves_per_simd", ctypes.c_int32), ("group_by_n", ctypes.c_int32 * (BATCH_MAX_QUBITS + 1)),
+                ("resident_max_n", ctypes.c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -102,6 +103,7 @@ def load_library() -> ctypes.CDLL:
         "qaoa_batch_create": [i32, vp, vp, vp, vp, i32, ctypes.POINTER(BatchOptions), pvp],
         "qaoa_batch_run": [vp, vp, vp, vp, vp, vp, vp],
         "qaoa_batch_destroy": [vp],
+        "qaoa_batch_timeline": [vp, vp, vp, vp],
         "qaoa_set_allocator": [ctypes.POINTER(Allocator)],
         "qaoa_mpnn_num_params": [i32, ctypes.POINTER(i64)],
         "qaoa_mpnn_create": [i32, pvp],
@@ -405,12 +407,12 @@ def qaoa_optimize(h, gamma, beta, max_iter=100, history=10, gtol=1e-8, ftol=0.0,
 
 
 def batch_options(steps=100, lr=0.05, beta1=0.9, beta2=0.999, eps=1e-8, workgroups=0, max_group=10,
-                  use_graph=True, waves_per_simd=1, group_by_n=None) -> BatchOptions:
+                  use_graph=True, waves_per_simd=1, group_by_n=None, resident_max_n=0) -> BatchOptions:
     gb = (ctypes.c_int32 * (BATCH_MAX_QUBITS + 1))()
     for n, k in (group_by_n or {}).items():
         gb[int(n)] = int(k)
     return BatchOptions(int(steps), float(lr), float(beta1), float(beta2), float(eps), int(workgroups),
-                        int(max_group), 1 if use_graph else 0, int(waves_per_simd), gb)
+                        int(max_group), 1 if use_graph else 0, int(waves_per_simd), gb, int(resident_max_n))
 
 
 def _graph_arrays(graphs):
@@ -459,6 +461,14 @@ def qaoa_batch_run(b, gamma0, beta0):
     _check(load_library().qaoa_batch_run(b, _ptr(g0), _ptr(b0), _ptr(g), _ptr(bb), _ptr(e0), _ptr(e1)),
            "qaoa_batch_run")
     return g, bb, e0, e1
+
+
+def qaoa_batch_timeline(b, count: int):
+    """(start_s, end_s, which_launch) per instance of the last run."""
+    t0, t1 = np.empty(count), np.empty(count)
+    which = np.empty(count, dtype=np.int32)
+    _check(load_library().qaoa_batch_timeline(b, _ptr(t0), _ptr(t1), _ptr(which)), "qaoa_batch_timeline")
+    return t0, t1, which
 
 
 def qaoa_batch_destroy(b) -> None:
@@ -699,6 +709,12 @@ class QaoaBatch:
         if self._b is None:
             raise ValueError("batch is closed")
         return qaoa_batch_run(self._b, gamma0, beta0)
+
+    def timeline(self):
+        """(start_s, end_s, which_launch) of every instance in the last run."""
+        if self._b is None:
+            raise ValueError("batch is closed")
+        return qaoa_batch_timeline(self._b, self.count)
 
     def close(self):
         if self._b is not None:

@@ -8,7 +8,11 @@ on a given device:
   qubits plus ceil((n - 12) / k) high passes of at most k qubits each, so
   smaller k means more, narrower passes over the slot;
 * the register budget of the engine kernel (``waves_per_simd``, 1 or 2);
-* the number of persistent workgroups (``workgroups``).
+* the number of persistent workgroups (``workgroups``);
+* the largest n run LDS-resident (``resident_max_n``, 0 or 12): instances of
+  at most 12 qubits are one tile, and may either stream through their slot
+  between passes within the main launch or keep both vectors in LDS in a
+  second launch of one workgroup per compute unit.
 
 ``tune`` times short runs of the actual batch (a couple of Adam steps per
 instance) over these candidates, keeps the fastest, and caches the choice in a
@@ -76,9 +80,9 @@ def tune(graphs: Sequence, p: int, cache: Optional[str] = DEFAULT_CACHE, probe_s
         with open(cache) as fh:
             table = json.load(fh)
         hit = table.get(dkey, {}).get(bkey)
-        if hit is not None and not force:
+        if hit is not None and not force and "resident_max_n" in hit:
             return hit
-    measured = {"depth": {}, "launch": {}}
+    measured = {"depth": {}, "launch": {}, "resident": {}}
     ns = sorted({int(g.n) for g in graphs})
     cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
     group_by_n = {}
@@ -107,13 +111,22 @@ def tune(graphs: Sequence, p: int, cache: Optional[str] = DEFAULT_CACHE, probe_s
     for wpe in (1, 2):
         for wg in (cus, 2 * cus):
             t = _time_run(graphs, p, g0, b0, probe_steps, waves_per_simd=wpe, workgroups=wg,
-                          group_by_n=group_by_n)
+                          group_by_n=group_by_n, resident_max_n=0)
             measured["launch"][f"wpe{wpe}:wg{wg}"] = t
             log(f"[tune] waves_per_simd={wpe} workgroups={wg}: {1e3 * t:.2f} ms")
             if best is None or t < best[0]:
                 best = (t, wpe, wg)
+    # 3) one-tile instances streamed within that launch or LDS-resident after it
+    resident = 0
+    if min(ns) <= 12:
+        t_res = _time_run(graphs, p, g0, b0, probe_steps, waves_per_simd=best[1], workgroups=best[2],
+                          group_by_n=group_by_n, resident_max_n=12)
+        measured["resident"] = {"0": best[0], "12": t_res}
+        log(f"[tune] resident_max_n=12: {1e3 * t_res:.2f} ms (streamed: {1e3 * best[0]:.2f} ms)")
+        resident = 12 if t_res < best[0] else 0
     choice = {"group_by_n": {str(k): v for k, v in group_by_n.items()}, "waves_per_simd": best[1],
-              "workgroups": best[2], "probe_steps": probe_steps, "measured": measured}
+              "workgroups": best[2], "resident_max_n": resident, "probe_steps": probe_steps,
+              "measured": measured}
     if cache:
         table.setdefault(dkey, {})[bkey] = choice
         os.makedirs(os.path.dirname(cache), exist_ok=True)
@@ -127,7 +140,8 @@ def tune(graphs: Sequence, p: int, cache: Optional[str] = DEFAULT_CACHE, probe_s
 def options_of(choice: Dict) -> Dict:
     """QaoaBatch keyword arguments of a tuning result."""
     return {"group_by_n": {int(k): int(v) for k, v in choice["group_by_n"].items()},
-            "waves_per_simd": int(choice["waves_per_simd"]), "workgroups": int(choice["workgroups"])}
+            "waves_per_simd": int(choice["waves_per_simd"]), "workgroups": int(choice["workgroups"]),
+            "resident_max_n": int(choice.get("resident_max_n", 0))}
 
 
 def cost_maxima(graphs) -> np.ndarray:

@@ -29,6 +29,7 @@ constexpr int kMaxBatchN = QAOA_BATCH_MAX_QUBITS;
 
 struct BatchArgs {
     int32_t count;
+    int32_t begin, end;     // this launch's range of the processing order
     const int32_t *order;   // processing order (largest n first)
     const int32_t *nq;      // [count] qubits
     const int64_t *eoff;    // [count + 1] edge offsets
@@ -45,7 +46,8 @@ struct BatchArgs {
     double2 *psi, *lam;     // slot arrays, `slot` amplitudes each
     double *cost;
     uint64_t slot;
-    uint32_t *counter;
+    uint32_t *counter;      // this launch's queue counter
+    uint64_t *ticks;        // [count][2] device wall clock at an instance's start and end
 };
 
 // Values every lane of the workgroup holds alike (read from LDS or loaded from
@@ -114,7 +116,7 @@ __device__ __forceinline__ void make_args(PassArgs &a, const BatchArgs &B, int n
 __device__ __forceinline__ void opaque(uint32_t &x) { asm volatile("" : "+s"(x)); }
 
 // All tiles of one pass, in order; sums accumulate in thread 0.
-template <int MODE>
+template <int MODE, bool RES = false>
 __device__ __forceinline__ void run_tiles(const PassArgs &a, uint64_t T, double2 *lds, double (&acc)[3])
 {
     for (uint64_t t = 0; t < T; ++t) {
@@ -128,8 +130,8 @@ __device__ __forceinline__ void run_tiles(const PassArgs &a, uint64_t T, double2
         opaque(b.geo.tmask);
         opaque(b.geo.tbits);
         double s[4];
-        if (b.tan_mode) tile_pass<double, MODE, true>(b, t, lds, s);
-        else tile_pass<double, MODE, false>(b, t, lds, s);
+        if (b.tan_mode) tile_pass<double, MODE, true, true, -1, RES>(b, t, lds, s);
+        else tile_pass<double, MODE, false, false, -1, RES>(b, t, lds, s);
         acc[0] += s[0];
         acc[1] += s[1];
         acc[2] += s[2];
@@ -296,29 +298,89 @@ __device__ __forceinline__ void wg_eval(const BatchArgs &B, int n, bool grad, co
         for (int i = 1; i <= 2 * p; ++i) out[i] *= 2.0;
 }
 
-__global__ __launch_bounds__(kThreads) void k_reset(uint32_t *c) { *c = 0u; }
-
-// WPE = waves per SIMD the register allocation is held to: 1 leaves room for
-// every value of the tile code, 2 hides more memory latency at the cost of a
-// few spilled registers.  The tuner measures both.
-template <int WPE>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_batch(BatchArgs B)
+// wg_eval for an instance of at most kTileBits qubits whose state and adjoint
+// vector live in LDS (psi, lam): every mixer layer is one pass over the single
+// tile, as in wg_eval with one group per layer.  The passes that hold one vector
+// transpose through lam's LDS (lam is dead then, or written at the pass's end),
+// the two-vector passes through psi's, after both vectors are in registers.
+__device__ __forceinline__ void wg_eval_res(const BatchArgs &B, int n, bool grad, const double *th,
+                                            double2 *psi, double2 *lam, double *cost, double *out)
 {
-    __shared__ double2 lds[kLdsTotal<double>];
+    const int p = B.p;
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0)
+        for (int i = 0; i <= 2 * p; ++i) out[i] = 0.0;
+    PassArgs a;
+    for (int l = 0; l < p; ++l) {
+        if (grad && l == p - 1) break;  // the turn pass
+        make_args(a, B, n, 0, uni(th[p + l]), psi, lam, cost);
+        a.flags |= kPhaseIn;
+        a.gamma_in = uni(th[l]);
+        if (l == 0) a.flags |= kInit;
+        if (l == p - 1) a.flags |= kEOut;
+        double acc[3] = {0.0, 0.0, 0.0};
+        run_tiles<kFwd, true>(a, 1, lam, acc);
+        if (tid == 0 && l == p - 1) out[0] = acc[0];
+    }
+    if (!grad) return;
+    {
+        const int l = p - 1;
+        make_args(a, B, n, 0, uni(th[p + l]), psi, lam, cost);
+        a.flags |= kPhaseIn | kPhaseOut;
+        a.gamma_in = a.gamma_out = uni(th[l]);
+        if (l == 0) a.flags |= kInit | kNoStore;
+        double acc[3] = {0.0, 0.0, 0.0};
+        run_tiles<kTurnPhase, true>(a, 1, lam, acc);
+        if (tid == 0) {
+            out[0] = acc[0];
+            out[1 + p + l] += acc[1];
+            out[1 + l] += acc[2];
+        }
+    }
+    for (int l = p - 2; l >= 0; --l) {
+        make_args(a, B, n, 0, uni(th[p + l]), psi, lam, cost);
+        a.flags |= kPhaseOut;
+        a.gamma_out = uni(th[l]);
+        if (l == 0) a.flags |= kNoStore;
+        double acc[3] = {0.0, 0.0, 0.0};
+        run_tiles<kBwd, true>(a, 1, psi, acc);
+        if (tid == 0) {
+            out[1 + p + l] += acc[1];
+            out[1 + l] += acc[2];
+        }
+    }
+    if (tid == 0)
+        for (int i = 1; i <= 2 * p; ++i) out[i] *= 2.0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_reset(uint32_t *c)
+{
+    c[0] = 0u;
+    c[1] = 0u;
+}
+
+// The queue loop of one launch.  RES: the instances are one tile each and their
+// state and adjoint vector stay in the LDS arrays lds0 / lds1 for the whole
+// optimisation; otherwise they live in the workgroup's slot and lds0 takes the
+// transposes.  The cost diagonal is in the slot either way.
+template <bool RES>
+__device__ __forceinline__ void engine(const BatchArgs &B, double2 *lds0, double2 *lds1)
+{
     __shared__ double th[2 * kMaxP], am[2 * kMaxP], av[2 * kMaxP], gr[2 * kMaxP + 1];
     __shared__ int sh_idx;
     const uint32_t tid = threadIdx.x;
-    double2 *psi = B.psi + (uint64_t)blockIdx.x * B.slot;
-    double2 *lam = B.lam + (uint64_t)blockIdx.x * B.slot;
+    double2 *psi = RES ? lds0 : B.psi + (uint64_t)blockIdx.x * B.slot;
+    double2 *lam = RES ? lds1 : B.lam + (uint64_t)blockIdx.x * B.slot;
     double *cost = B.cost + (uint64_t)blockIdx.x * B.slot;
     const int p = B.p;
     for (;;) {
-        if (tid == 0) sh_idx = (int)atomicAdd(B.counter, 1u);
+        if (tid == 0) sh_idx = B.begin + (int)atomicAdd(B.counter, 1u);
         __syncthreads();
         const int idx = uni(sh_idx);
         __syncthreads();
-        if (idx >= B.count) return;
+        if (idx >= B.end) return;
         const int i = uni(B.order[idx]);
+        if (tid == 0) B.ticks[2 * (int64_t)i] = wall_clock64();
         const int n = uni(B.nq[i]);
         const uint64_t N = 1ull << n;
         // cost diagonal: sum of cut edge weights in edge order
@@ -344,7 +406,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WPE, W
         // copy of the pass code in the kernel)
         for (int step = 0;; ++step) {
             const bool last = step == B.steps;
-            wg_eval(B, n, !last, th, lds, psi, lam, cost, gr);
+            if constexpr (RES) wg_eval_res(B, n, !last, th, psi, lam, cost, gr);
+            else wg_eval(B, n, !last, th, lds0, psi, lam, cost, gr);
             __syncthreads();
             if (tid == 0 && step == 0) B.e_first[i] = gr[0];
             if (last) {
@@ -366,8 +429,27 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WPE, W
             if (tid < p) B.gamma[(int64_t)i * p + tid] = th[tid];
             else B.beta[(int64_t)i * p + tid - p] = th[tid];
         }
+        if (tid == 0) B.ticks[2 * (int64_t)i + 1] = wall_clock64();
         __syncthreads();
     }
+}
+
+// WPE = waves per SIMD the register allocation is held to: 1 leaves room for
+// every value of the tile code, 2 hides more memory latency at the cost of a
+// few spilled registers.  The tuner measures both.
+template <int WPE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_batch(BatchArgs B)
+{
+    __shared__ double2 lds[kLdsTotal<double>];
+    engine<false>(B, lds, lds);
+}
+
+// Instances of at most kTileBits qubits with both vectors resident in LDS
+// (2 x 68 KiB: one workgroup per compute unit).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_batch_res(BatchArgs B)
+{
+    __shared__ double2 lds_psi[kLdsTotal<double>], lds_lam[kLdsTotal<double>];
+    engine<true>(B, lds_psi, lds_lam);
 }
 
 }  // namespace
@@ -377,10 +459,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WPE, W
 
 struct qaoa_batch_s {
     int count = 0, p = 0, nmax = 0, device = 0, workgroups = 0, wpe = 1;
+    int split = 0;            // instances [0, split) of the order are streamed, the rest LDS-resident
+    int res_workgroups = 0;   // grid of the LDS-resident launch
+    int resident_max_n = 0;
+    bool ran = false;
     int64_t edges_total = 0;
     hipStream_t stream = nullptr;
     std::vector<void *> allocs;
-    qk::BatchArgs args{};
+    std::vector<int32_t> order, nq;
+    qk::BatchArgs args{}, args_res{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool use_graph = true;
@@ -418,11 +505,17 @@ qaoa_status launch_engine(qaoa_batch b)
 {
     hipLaunchKernelGGL(qk::k_reset, dim3(1), dim3(1), 0, b->stream, b->args.counter);
     BCHECK(b, hipGetLastError());
-    if (b->wpe == 2)
-        hipLaunchKernelGGL(qk::k_batch<2>, dim3(b->workgroups), dim3(qk::kThreads), 0, b->stream, b->args);
-    else
-        hipLaunchKernelGGL(qk::k_batch<1>, dim3(b->workgroups), dim3(qk::kThreads), 0, b->stream, b->args);
-    BCHECK(b, hipGetLastError());
+    if (b->split > 0) {
+        const dim3 grid(std::min(b->workgroups, b->split));
+        if (b->wpe == 2) hipLaunchKernelGGL(qk::k_batch<2>, grid, dim3(qk::kThreads), 0, b->stream, b->args);
+        else hipLaunchKernelGGL(qk::k_batch<1>, grid, dim3(qk::kThreads), 0, b->stream, b->args);
+        BCHECK(b, hipGetLastError());
+    }
+    if (b->split < b->count) {
+        hipLaunchKernelGGL(qk::k_batch_res, dim3(b->res_workgroups), dim3(qk::kThreads), 0, b->stream,
+                           b->args_res);
+        BCHECK(b, hipGetLastError());
+    }
     return QAOA_OK;
 }
 
@@ -452,7 +545,8 @@ qaoa_status qaoa_batch_create(int32_t count, const int32_t *n, const int64_t *ed
             return bfail(QAOA_ERR_INVALID_ARGUMENT, "group_by_n entries must be in [0, 10]");
     if (o.steps < 0 || !(o.lr > 0.0) || !(o.beta1 >= 0.0 && o.beta1 < 1.0) ||
         !(o.beta2 >= 0.0 && o.beta2 < 1.0) || !(o.eps > 0.0) || o.workgroups < 0 ||
-        o.max_group < 1 || o.max_group > 10 || o.waves_per_simd < 0 || o.waves_per_simd > 2)
+        o.max_group < 1 || o.max_group > 10 || o.waves_per_simd < 0 || o.waves_per_simd > 2 ||
+        o.resident_max_n < 0 || o.resident_max_n > qk::kTileBits)
         return bfail(QAOA_ERR_INVALID_ARGUMENT, "invalid options");
     if (edge_offsets[0] != 0) return bfail(QAOA_ERR_INVALID_ARGUMENT, "edge_offsets[0] must be 0");
     int nmax = 0;
@@ -485,6 +579,7 @@ qaoa_status qaoa_batch_create(int32_t count, const int32_t *n, const int64_t *ed
     b->edges_total = E;
     b->use_graph = o.use_graph != 0;
     b->wpe = o.waves_per_simd == 2 ? 2 : 1;
+    b->resident_max_n = o.resident_max_n;
     auto cleanup = [&](qaoa_status st) {
         std::string keep = qk::error_message();
         qaoa_batch_destroy(b);
@@ -504,6 +599,11 @@ qaoa_status qaoa_batch_create(int32_t count, const int32_t *n, const int64_t *ed
         per_cu = 1;
     b->workgroups = o.workgroups > 0 ? o.workgroups : per_cu * prop.multiProcessorCount;
     b->workgroups = std::min(b->workgroups, count);
+    int per_cu_res = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_res, qk::k_batch_res, qk::kThreads, 0) !=
+            hipSuccess ||
+        per_cu_res < 1)
+        per_cu_res = 1;
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
         return cleanup(bfail(QAOA_ERR_DEVICE, "stream creation failed"));
 
@@ -526,6 +626,15 @@ qaoa_status qaoa_batch_create(int32_t count, const int32_t *n, const int64_t *ed
     std::vector<int32_t> order(count);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n[a] > n[c]; });
+    // the largest-first order puts the LDS-resident instances (one pass per layer) at its end
+    b->split = count;
+    while (b->split > 0 && n[order[b->split - 1]] <= o.resident_max_n) --b->split;
+    for (int i = b->split; i < count; ++i)
+        if (npass[n[order[i]]] != 1) return cleanup(bfail(QAOA_ERR_UNSUPPORTED, "resident instance with several passes"));
+    // the resident launch uses the first res_workgroups slots' cost areas
+    b->res_workgroups = std::min({per_cu_res * prop.multiProcessorCount, b->workgroups, std::max(count - b->split, 1)});
+    b->order = order;
+    b->nq.assign(n, n + count);
 
     qk::BatchArgs &A = b->args;
     qaoa_status st;
@@ -535,6 +644,7 @@ qaoa_status qaoa_batch_create(int32_t count, const int32_t *n, const int64_t *ed
     qk::Geometry *d_geo;
     double2 *d_psi, *d_lam;
     uint32_t *d_cnt;
+    uint64_t *d_ticks;
     if ((st = upload(b, &d_order, order.data(), count)) != QAOA_OK ||
         (st = upload(b, &d_n, n, count)) != QAOA_OK ||
         (st = upload(b, &d_eoff, edge_offsets, (size_t)count + 1)) != QAOA_OK ||
@@ -550,9 +660,13 @@ qaoa_status qaoa_batch_create(int32_t count, const int32_t *n, const int64_t *ed
         (st = upload<double2>(b, &d_psi, nullptr, (size_t)b->workgroups * slot)) != QAOA_OK ||
         (st = upload<double2>(b, &d_lam, nullptr, (size_t)b->workgroups * slot)) != QAOA_OK ||
         (st = upload<double>(b, &d_cost, nullptr, (size_t)b->workgroups * slot)) != QAOA_OK ||
-        (st = upload<uint32_t>(b, &d_cnt, nullptr, 1)) != QAOA_OK)
+        (st = upload<uint32_t>(b, &d_cnt, nullptr, 2)) != QAOA_OK ||
+        (st = upload<uint64_t>(b, &d_ticks, nullptr, (size_t)count * 2)) != QAOA_OK)
         return cleanup(st);
     A.count = count;
+    A.begin = 0;
+    A.end = b->split;
+    A.ticks = d_ticks;
     A.order = d_order;
     A.nq = d_n;
     A.eoff = d_eoff;
@@ -576,6 +690,10 @@ qaoa_status qaoa_batch_create(int32_t count, const int32_t *n, const int64_t *ed
     A.cost = d_cost;
     A.slot = slot;
     A.counter = d_cnt;
+    b->args_res = A;
+    b->args_res.begin = b->split;
+    b->args_res.end = count;
+    b->args_res.counter = d_cnt + 1;
     if (hipStreamSynchronize(b->stream) != hipSuccess) return cleanup(bfail(QAOA_ERR_DEVICE, "upload failed"));
 
     if (b->use_graph) {
@@ -631,6 +749,31 @@ qaoa_status qaoa_batch_run(qaoa_batch b, const double *gamma0, const double *bet
     if (e_first) BCHECK(b, hipMemcpyAsync(e_first, A.e_first, b->count * 8, hipMemcpyDeviceToHost, b->stream));
     if (e_last) BCHECK(b, hipMemcpyAsync(e_last, A.e_last, b->count * 8, hipMemcpyDeviceToHost, b->stream));
     BCHECK(b, hipStreamSynchronize(b->stream));
+    b->ran = true;
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_batch_timeline(qaoa_batch b, double *start_s, double *end_s, int32_t *which_launch)
+{
+    if (!b) return bfail(QAOA_ERR_INVALID_ARGUMENT, "batch is NULL");
+    if (!b->ran) return bfail(QAOA_ERR_INVALID_ARGUMENT, "the batch has not run yet");
+    if (b->poisoned) return bfail(QAOA_ERR_DEVICE, "batch is unusable after an earlier device error");
+    int rate_khz = 0;
+    BCHECK(b, hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, b->device));
+    if (rate_khz <= 0) return bfail(QAOA_ERR_DEVICE, "device wall clock rate unknown");
+    std::vector<uint64_t> t((size_t)b->count * 2);
+    BCHECK(b, hipMemcpyAsync(t.data(), b->args.ticks, t.size() * 8, hipMemcpyDeviceToHost, b->stream));
+    BCHECK(b, hipStreamSynchronize(b->stream));
+    uint64_t t0 = ~0ull;
+    for (int i = 0; i < b->count; ++i) t0 = std::min(t0, t[2 * (size_t)i]);
+    const double tick = 1.0 / (1e3 * (double)rate_khz);
+    std::vector<int32_t> which(b->count, 0);
+    for (int k = b->split; k < b->count; ++k) which[b->order[k]] = 1;
+    for (int i = 0; i < b->count; ++i) {
+        if (start_s) start_s[i] = (double)(int64_t)(t[2 * (size_t)i] - t0) * tick;
+        if (end_s) end_s[i] = (double)(int64_t)(t[2 * (size_t)i + 1] - t0) * tick;
+        if (which_launch) which_launch[i] = which[i];
+    }
     return QAOA_OK;
 }
 

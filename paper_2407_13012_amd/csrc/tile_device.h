@@ -662,7 +662,10 @@ __device__ __forceinline__ void st(T v, T *p, bool stream)
 // One pass over tile t: load, [phase], rotations, [E / adjoint terms / phase
 // undo], store.  The workgroup's sums of the E, <lam|X|phi> and <lam|C|phi>
 // terms are returned in sums[0..2] (valid in thread 0; zero when not taken).
-template <typename R, int MODE, bool TM, bool TM2 = TM, int SP = -1>
+// RES: psi and lam point into LDS (a whole one-tile instance held there), and
+// a two-vector pass may take the LDS of psi for its transposes, so all loads
+// of the tile complete before the first transpose writes.
+template <typename R, int MODE, bool TM, bool TM2 = TM, int SP = -1, bool RES = false>
 __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typename Tr<R>::V *lds,
                                           double (&sums)[4])
 {
@@ -681,7 +684,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
     const bool full = g.tbits == (uint32_t)Tr<R>::TB;
     const uint32_t lim = 1u << g.tbits;
     const Targets<SP> tg{g.tmask};
-    const bool strm = (a.flags & kStream) != 0;
+    const bool strm = !RES && (a.flags & kStream) != 0;
     V *psi = (V *)a.psi;
     V *lam = (V *)a.lam;
     const CT *cost = (const CT *)a.cost;
@@ -907,6 +910,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
             }
         }
         if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
+        if constexpr (RES) __syncthreads();
         const R mb = (R)a.mul_b;
         const double f2 = a.fac_b * a.fac_b;
         double sig2 = 1.0;

@@ -238,7 +238,8 @@ def test_batch_create_rejects(lib, case):
 @pytest.mark.parametrize("field,value", [("steps", -1), ("lr", 0.0), ("beta1", 1.0), ("beta2", -0.1),
                                          ("eps", 0.0), ("workgroups", -2), ("max_group", 0),
                                          ("max_group", 11), ("waves_per_simd", 3),
-                                         ("waves_per_simd", -1)])
+                                         ("waves_per_simd", -1), ("resident_max_n", -1),
+                                         ("resident_max_n", 13)])
 def test_batch_create_rejects_options(lib, field, value):
     from paper_2407_13012_amd import batch_options
     opt = batch_options()
@@ -251,6 +252,7 @@ def test_batch_create_rejects_options(lib, field, value):
 def test_batch_run_rejects(lib):
     g = np.zeros(2)
     assert lib.qaoa_batch_run(None, g.ctypes.data, g.ctypes.data, None, None, None, None) == 1
+    assert lib.qaoa_batch_timeline(None, None, None, None) == 1
     assert lib.qaoa_batch_destroy(None) == 0
 
 

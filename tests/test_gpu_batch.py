@@ -224,3 +224,54 @@ def test_batch_matches_single_instance_library():
         np.testing.assert_allclose(np.r_[gam[i], bet[i]], x, rtol=0, atol=1e-9)
         assert abs(e0[i] - E_first) <= 1e-10 * max(1.0, 1.0 / sc)
         assert abs(e1[i] - E_last) <= 1e-9 * max(1.0, 1.0 / sc)
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_batch_lds_resident_matches_streamed_and_oracle(p):
+    """One-tile instances (n <= 12) whose state and adjoint vector stay in LDS
+    for all their Adam steps (a second launch, one workgroup per compute unit)
+    give the results of the same instances streamed through their slots; a
+    threshold below 12 splits the one-tile sizes between the two launches."""
+    sizes = [12, 2, 9, 13, 5, 11, 3, 15, 10, 12, 7]
+    graphs = family(sizes, seed=90 + p)
+    g0, b0 = start_angles(graphs, p, seed=p + 20)
+    ref = run_batch(graphs, p, g0, b0, steps=4, workgroups=3, resident_max_n=0)
+    res = run_batch(graphs, p, g0, b0, steps=4, workgroups=3, resident_max_n=12)
+    mid = run_batch(graphs, p, g0, b0, steps=4, workgroups=3, resident_max_n=9)
+    for alt in (res, mid):
+        for a, c in zip(ref, alt):
+            np.testing.assert_allclose(a, c, rtol=0, atol=1e-12)
+    check_against_oracle(graphs, p, g0, b0, res, steps=4)
+
+
+def test_batch_all_resident_single_workgroup_and_replay():
+    """Every instance LDS-resident (the streamed launch is skipped), all of them
+    queued on one workgroup, replayed from the graph and launched eagerly."""
+    from paper_2407_13012_amd import QaoaBatch
+    graphs = family([12, 4, 8, 11, 12], seed=95)
+    g0, b0 = start_angles(graphs, 2, seed=11)
+    with QaoaBatch(graphs, 2, steps=3, workgroups=1, resident_max_n=12) as b:
+        r1 = b.run(g0, b0)
+        r2 = b.run(g0, b0)
+    r3 = run_batch(graphs, 2, g0, b0, steps=3, workgroups=7, resident_max_n=12, use_graph=False)
+    for a, c, d in zip(r1, r2, r3):
+        np.testing.assert_array_equal(a, c)
+        np.testing.assert_array_equal(a, d)
+    check_against_oracle(graphs, 2, g0, b0, r1, steps=3)
+
+
+def test_batch_timeline():
+    """Per-instance start and end times of the last run: the streamed launch's
+    instances, then (same stream) the LDS-resident ones."""
+    from paper_2407_13012_amd import QaoaBatch, QaoaError
+    graphs = family([14, 12, 9, 13, 6, 16], seed=97)
+    g0, b0 = start_angles(graphs, 2, seed=12)
+    with QaoaBatch(graphs, 2, steps=2, workgroups=2, resident_max_n=12) as b:
+        with pytest.raises(QaoaError):
+            b.timeline()
+        b.run(g0, b0)
+        t0, t1, which = b.timeline()
+    np.testing.assert_array_equal(which, [0, 1, 1, 0, 1, 0])
+    assert t0.min() == 0.0 and np.all(t1 > t0)
+    assert t0[which == 1].min() >= t1[which == 0].max() - 1e-6
+    assert t1.max() < 10.0
