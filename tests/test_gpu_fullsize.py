@@ -133,3 +133,27 @@ def test_headline_qubo_cost_entries_and_bounds_n32():
         assert E == E2 and np.array_equal(dg, dg2) and np.array_equal(db, db2)
         assert lo <= E <= hi
         assert np.all(np.isfinite(dg)) and np.all(np.isfinite(db))
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_block_qubo_mixed_rotation_forms_n32(prec):
+    """Mixer angles on both sides of pi/4 (the rotations' tan and cot forms)
+    in the n = 32 sweeps, whose plain forward sweeps take two tiles per
+    workgroup; E and the gradient against the block-wise oracle."""
+    inst = qi.qubo_blocks(N, 8, 0.5, seed=22)
+    gamma = np.array([0.35, 0.6, 0.8])
+    beta = np.array([1.1, 0.45, 1.3])
+    E_ref, dg_ref, db_ref, _ = block_reference(inst, 8, gamma, beta)
+    with H(inst, prec) as q:
+        E, dg, db = q.gradient(gamma, beta)
+        E_ev = q.evaluate(gamma, beta)
+    wsum = np.abs(inst.J).sum() + np.abs(inst.h).sum()
+    if prec == "c128":
+        tol = 1e-10 * wsum
+        assert abs(E - E_ref) <= tol and abs(E_ev - E_ref) <= tol
+        assert np.max(np.abs(dg - dg_ref)) <= 1e-8 and np.max(np.abs(db - db_ref)) <= 1e-8
+    else:
+        gscale = max(np.abs(np.concatenate([dg_ref, db_ref])).max(), 1.0)
+        assert abs(E - E_ref) / max(abs(E_ref), 1.0) <= 1e-4
+        assert abs(E_ev - E_ref) / max(abs(E_ref), 1.0) <= 1e-4
+        assert np.abs(np.concatenate([dg - dg_ref, db - db_ref])).max() / gscale <= 1e-4
