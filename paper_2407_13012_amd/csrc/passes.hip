@@ -113,6 +113,83 @@ __global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>
     }
 }
 
+// The first sweep of an evolution (layer 1's phase on the uniform state, then
+// its first mixer group: no state is read, the cost entries are), two tiles per
+// workgroup: tiles of the first group are runs of 4096 amplitudes, so here the
+// pair gains nothing in cache lines, but the two tiles' independent arithmetic
+// (sincos of every entry, rotations, transposes) interleaves, as in the
+// two-vector sweeps.  The arithmetic per amplitude is tile_pass's for kFwd
+// with kInit | kPhaseIn, so results are bitwise the same.  Its runs are long,
+// so its accesses are nontemporal (kStream, which the launcher requires).
+template <typename R, bool TM>
+__global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>::MINW))) void k_init_pair(PassArgs a)
+{
+    using V = typename Tr<R>::V;
+    using CT = typename Tr<R>::CT;
+    constexpr int WB = Tr<R>::WB, NR = Tr<R>::NR, SP = 0;
+    __shared__ V lds[kLdsTotal<R>];
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const Geometry &g = a.geo;
+    const Targets<SP> tg{g.tmask};
+    const uint64_t t0 = 2 * xcd_tile(blockIdx.x, a.xcd_g);
+    const uint64_t b0 = tile_base(t0, g), b1 = tile_base(t0 + 1, g);
+    const CT *cost = (const CT *)a.cost;
+    CT cu[NR], cw[NR];
+    {
+        const uint64_t pA = dep(elem<0, WB>(lane, wave, 0), g);
+        const RegOffsets<0, WB> off(g);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            cu[r] = ldnt(&cost[b0 | pA | off(r)]);
+            cw[r] = ldnt(&cost[b1 | pA | off(r)]);
+        }
+    }
+    __builtin_amdgcn_s_setprio(0);
+    const V a0 = {(R)a.amp0, (R)0};
+    V u[NR], w[NR];
+    {
+        // four entries at a time: left to itself the scheduler overlaps all 32
+        // evaluations and runs out of registers
+        const auto PK = phase_consts<R>(-a.gamma_in);
+#pragma unroll
+        for (int h = 0; h < NR; h += 4) {
+#pragma unroll
+            for (int r = h; r < h + 4; ++r) {
+                R c, s;
+                phase_cs(-a.gamma_in, cu[r], c, s, PK);
+                u[r] = cmul(a0, c, s);
+                phase_cs(-a.gamma_in, cw[r], c, s, PK);
+                w[r] = cmul(a0, c, s);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    const R mf = (R)a.mul_f;
+    mix_stage<0, TM, true>(u, mf, tg);
+    mix_stage<0, TM, true>(w, mf, tg);
+    xpose<0, 1>(u, lds, lane, wave);
+    xpose<0, 1>(w, lds, lane, wave);
+    mix_stage<1, TM, true>(u, mf, tg);
+    mix_stage<1, TM, true>(w, mf, tg);
+    xpose<1, 2>(u, lds, lane, wave);
+    xpose<1, 2>(w, lds, lane, wave);
+    mix_stage<2, TM, true>(u, mf, tg);
+    mix_stage<2, TM, true>(w, mf, tg);
+    const R sf = (R)a.scl_f;
+    V *psi = (V *)a.psi;
+    uint32_t tid2 = threadIdx.x;
+    asm volatile("" : "+v"(tid2));
+    const uint64_t pC = dep(elem<2, WB>(tid2 & 63u, tid2 >> 6, 0), g);
+    const RegOffsets<2, WB> off(g);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        stnt(vscale(u[r], sf), &psi[b0 | pC | off(r)]);
+        stnt(vscale(w[r], sf), &psi[b1 | pC | off(r)]);
+    }
+}
+
 // Layer-boundary passes (kFwdFuse, kBwdFuse); TM / TM2 are the factored forms
 // of the two rotations.  Same tile order and partial layout as k_pass.
 template <typename R, int MODE, bool TM, bool TM2, int SP>
@@ -136,15 +213,37 @@ __global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>
     }
 }
 
+// Arguments of a tile-pair launch: the XCD grouping must divide the number of
+// pairs (xcd_tile is a permutation of [0, count) only when 8 * 2^G divides count).
+PassArgs pair_args(const PassArgs &a, uint64_t pairs)
+{
+    PassArgs b = a;
+    b.xcd_g = 0;
+    for (uint32_t g = a.xcd_g; g >= 1; --g)
+        if (pairs % (8ull << g) == 0) {
+            b.xcd_g = g;
+            break;
+        }
+    return b;
+}
+
 template <typename R, bool TM, int SP>
 void launch_single(int mode, const PassArgs &a, dim3 grid, hipStream_t s)
 {
     const dim3 block(Tr<R>::NT);
+    if constexpr (SP == 0) {
+        // the first sweep of an evolution in tile pairs (an even number of full tiles)
+        if (mode == kFwd && a.flags == (kInit | kPhaseIn | kStream) && a.geo.tbits == (uint32_t)Tr<R>::TB &&
+            grid.x % 2 == 0 && grid.x >= 2) {
+            hipLaunchKernelGGL((k_init_pair<R, TM>), dim3(grid.x / 2), block, 0, s, pair_args(a, grid.x / 2));
+            return;
+        }
+    }
     if constexpr (SP == kPairSP<R>) {
         // plain forward sweeps in tile pairs (an even number of full tiles)
         constexpr int kPlainMask = kInit | kPhaseIn | kEOut | kNoStore | kStream;
         if (mode == kFwd && !(a.flags & kPlainMask) && grid.x % 2 == 0 && grid.x >= 2) {
-            hipLaunchKernelGGL((k_fwd_pair<R, TM>), dim3(grid.x / 2), block, 0, s, a);
+            hipLaunchKernelGGL((k_fwd_pair<R, TM>), dim3(grid.x / 2), block, 0, s, pair_args(a, grid.x / 2));
             return;
         }
     }
