@@ -217,12 +217,7 @@ qk::PassArgs pass_args(qaoa_handle h, const qk::PassPlan &pp, double beta)
     // short runs the L2 must keep each line for the neighbouring tile.
     if (a.geo.t_dst[0] == 0 && a.geo.t_len[0] >= 6) a.flags |= qk::kStream;
     // Send 16 consecutive tiles (adjacent runs, shared lines and DRAM rows) to one XCD.
-    const uint64_t T = nblocks(h);
-    for (uint32_t g = 4; g >= 1; --g)
-        if (T % (8ull << g) == 0) {
-            a.xcd_g = g;
-            break;
-        }
+    a.xcd_g = qk::xcd_group_bits(nblocks(h), 4);
     a.amp0 = 1.0 / std::sqrt((double)h->N);
     // Factored rotations: exp(-i b X) = f (p I - i q X) with the larger of
     // |cos b|, |sin b| as f, so the non-unit coefficient has magnitude <= 1.

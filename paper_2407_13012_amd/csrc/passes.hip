@@ -30,10 +30,7 @@ __global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(MODE 
 {
     __shared__ typename Tr<R>::V lds[kLdsTotal<R>];
     const uint64_t b = blockIdx.x;
-    // 2^G consecutive tiles per XCD: workgroups are dealt to the 8 XCDs in turn
-    const uint32_t G = a.xcd_g;
-    const uint64_t t = G ? ((b & ~((8ull << G) - 1ull)) | ((b & 7ull) << G) | ((b >> 3) & ((1ull << G) - 1ull)))
-                         : b;
+    const uint64_t t = xcd_tile(b, a.xcd_g);
     double sums[4];
     tile_pass<R, MODE, TM, TM, SP>(a, t, lds, sums);
     // one partial per workgroup
@@ -42,13 +39,6 @@ __global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(MODE 
         if (MODE != kFwd) a.part_b[b] = (a.flags & kBetaAcc) ? a.part_b[b] + sums[1] : sums[1];
         if (MODE == kTurnPhase || (MODE == kBwd && (a.flags & kPhaseOut))) a.part_g[b] = sums[2];
     }
-}
-
-// Tile of linear index L in the order that deals 2^G consecutive tiles to each
-// XCD (workgroups go to the 8 XCDs in turn).
-__device__ __forceinline__ uint64_t xcd_tile(uint64_t L, uint32_t G)
-{
-    return G ? ((L & ~((8ull << G) - 1ull)) | ((L & 7ull) << G) | ((L >> 3) & ((1ull << G) - 1ull))) : L;
 }
 
 // Spectator class whose runs are 64 bytes: 4 complex128 or 8 complex64 amplitudes.
@@ -197,9 +187,7 @@ __global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>
 {
     __shared__ typename Tr<R>::V lds[kLdsTotal<R>];
     const uint64_t b = blockIdx.x;
-    const uint32_t G = a.xcd_g;
-    const uint64_t t = G ? ((b & ~((8ull << G) - 1ull)) | ((b & 7ull) << G) | ((b >> 3) & ((1ull << G) - 1ull)))
-                         : b;
+    const uint64_t t = xcd_tile(b, a.xcd_g);
     if constexpr (MODE == kFwdFuse) {
         tile_pass_fwd_fuse<R, TM, TM2, SP>(a, t, lds);
     } else {
@@ -218,12 +206,7 @@ __global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>
 PassArgs pair_args(const PassArgs &a, uint64_t pairs)
 {
     PassArgs b = a;
-    b.xcd_g = 0;
-    for (uint32_t g = a.xcd_g; g >= 1; --g)
-        if (pairs % (8ull << g) == 0) {
-            b.xcd_g = g;
-            break;
-        }
+    b.xcd_g = xcd_group_bits(pairs, a.xcd_g);
     return b;
 }
 

@@ -105,6 +105,22 @@ struct PassArgs {
     double *part_b2;    // <lam|X|phi> partials of the second rotation's layer
 };
 
+// Tile visited by workgroup L when 2^G consecutive tiles go to each XCD
+// (workgroups are dealt to the 8 XCDs in turn): tiles that share cache lines
+// and DRAM rows then meet in one XCD's L2.  A permutation of [0, count) when
+// 8 * 2^G divides count.
+__host__ __device__ inline uint64_t xcd_tile(uint64_t L, uint32_t G)
+{
+    return G ? ((L & ~((8ull << G) - 1ull)) | ((L & 7ull) << G) | ((L >> 3) & ((1ull << G) - 1ull))) : L;
+}
+// The largest G <= gmax for which xcd_tile permutes [0, count); 0 if none.
+inline uint32_t xcd_group_bits(uint64_t count, uint32_t gmax)
+{
+    for (uint32_t g = gmax; g >= 1; --g)
+        if (count % (8ull << g) == 0) return g;
+    return 0;
+}
+
 // Launchers; all return the launch status.  `c64` selects complex64/fp32 cost.
 hipError_t launch_pass(int mode, bool c64, const PassArgs &a, uint64_t nblocks, hipStream_t s);
 // Pass kernels of one precision (R = double: complex128, float: complex64)

@@ -1,5 +1,5 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer: the pass
-planner over every size and cap, the cost-diagonal pieces against the plain
+planner over every size and cap, the tile order of the pass launches, the cost-diagonal pieces against the plain
 definition of the cost, the L-BFGS driver on Rosenbrock and on
 objectives that fail or stop, and the CPU oracle's routines on small instances.
 Built with the host compilers only (no GPU code)."""
@@ -32,6 +32,14 @@ def test_planner_under_sanitizers(tmp_path):
                          [os.path.join(HOST, "plan_check.cpp"), os.path.join(CSRC, "plan.cpp")],
                          ["-D__HIP_PLATFORM_AMD__", "-I", ROCM_INCLUDE])
     assert "plans ok" in out
+
+
+@pytest.mark.skipif(shutil.which("g++") is None or not os.path.isdir(ROCM_INCLUDE),
+                    reason="needs g++ and the HIP headers")
+def test_tile_order_under_sanitizers(tmp_path):
+    out = _build_and_run(tmp_path, "xcd_check", [os.path.join(HOST, "xcd_check.cpp")],
+                         ["-D__HIP_PLATFORM_AMD__", "-I", ROCM_INCLUDE])
+    assert "tile order ok" in out
 
 
 @pytest.mark.skipif(shutil.which("g++") is None or not os.path.isdir(ROCM_INCLUDE),
