@@ -41,23 +41,20 @@ __global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(MODE 
     }
 }
 
-// Spectator class whose runs are 64 bytes: 4 complex128 or 8 complex64 amplitudes.
-template <typename R>
-constexpr int kPairSP = sizeof(R) == 8 ? 2 : 3;
-
-// Plain forward sweep (no phase, no E, full tiles) of a pass with 64-byte
-// runs, two tiles per workgroup: the tiles 2i and 2i + 1 differ in the lowest
-// free bit, the bit above the spectators, so each run of one is the other half
-// of a 128-byte cache line of the other, and one workgroup reads whole lines;
-// twice the bytes per workgroup are in flight, as in the two-vector sweeps.
-// The two tiles are rotated in step (stages and transposes interleaved), as
-// the backward sweep does with its two vectors.  Measured at n = 32: 25.2 vs
+// Plain forward sweep (no phase, no E, full tiles of spectator class SP), two
+// tiles per workgroup: tiles 2i and 2i + 1, which differ in the lowest free
+// bit.  With 64-byte runs (4 complex128 or 8 complex64 amplitudes) each run of
+// one is the other half of a 128-byte cache line of the other, so one
+// workgroup reads whole lines; in every class twice the bytes per workgroup
+// are in flight and the two tiles' stages and transposes interleave, as the
+// backward sweep does with its two vectors.  Measured at n = 32: 25.2 vs
 // 27.2 ms per complex128 sweep, 12.9 vs 14.9 ms per complex64 sweep.
-template <typename R, bool TM>
+template <typename R, bool TM, int SP>
 __global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>::MINW))) void k_fwd_pair(PassArgs a)
 {
     using V = typename Tr<R>::V;
-    constexpr int WB = Tr<R>::WB, NR = Tr<R>::NR, SP = kPairSP<R>;
+    constexpr int WB = Tr<R>::WB, NR = Tr<R>::NR;
+    constexpr bool strm = stream_class(SP);
     __shared__ V lds[kLdsTotal<R>];
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
@@ -73,8 +70,8 @@ __global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>
         const RegOffsets<0, WB> off(g);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            u[r] = psi[b0 | pA | off(r)];
-            w[r] = psi[b1 | pA | off(r)];
+            u[r] = ld(&psi[b0 | pA | off(r)], strm);
+            w[r] = ld(&psi[b1 | pA | off(r)], strm);
         }
     }
     // (measured: with this priority instruction after the loads the complex128
@@ -83,12 +80,18 @@ __global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>
     const R mf = (R)a.mul_f;
     mix_stage<0, TM, true>(u, mf, tg);
     mix_stage<0, TM, true>(w, mf, tg);
-    xpose<0, 1>(u, lds, lane, wave);
-    xpose<0, 1>(w, lds, lane, wave);
-    mix_stage<1, TM, true>(u, mf, tg);
-    mix_stage<1, TM, true>(w, mf, tg);
-    xpose<1, 2>(u, lds, lane, wave);
-    xpose<1, 2>(w, lds, lane, wave);
+    if constexpr (SP >= 4 && WB == 2) {
+        // complex128 with no target among B's register bits: A to C directly
+        xpose<0, 2>(u, lds, lane, wave);
+        xpose<0, 2>(w, lds, lane, wave);
+    } else {
+        xpose<0, 1>(u, lds, lane, wave);
+        xpose<0, 1>(w, lds, lane, wave);
+        mix_stage<1, TM, true>(u, mf, tg);
+        mix_stage<1, TM, true>(w, mf, tg);
+        xpose<1, 2>(u, lds, lane, wave);
+        xpose<1, 2>(w, lds, lane, wave);
+    }
     mix_stage<2, TM, true>(u, mf, tg);
     mix_stage<2, TM, true>(w, mf, tg);
     const R sf = (R)a.scl_f;
@@ -98,8 +101,8 @@ __global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>
     const RegOffsets<2, WB> off(g);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        psi[b0 | pC | off(r)] = vscale(u[r], sf);
-        psi[b1 | pC | off(r)] = vscale(w[r], sf);
+        st(vscale(u[r], sf), &psi[b0 | pC | off(r)], strm);
+        st(vscale(w[r], sf), &psi[b1 | pC | off(r)], strm);
     }
 }
 
@@ -222,11 +225,15 @@ void launch_single(int mode, const PassArgs &a, dim3 grid, hipStream_t s)
             return;
         }
     }
-    if constexpr (SP == kPairSP<R>) {
-        // plain forward sweeps in tile pairs (an even number of full tiles)
-        constexpr int kPlainMask = kInit | kPhaseIn | kEOut | kNoStore | kStream;
-        if (mode == kFwd && !(a.flags & kPlainMask) && grid.x % 2 == 0 && grid.x >= 2) {
-            hipLaunchKernelGGL((k_fwd_pair<R, TM>), dim3(grid.x / 2), block, 0, s, pair_args(a, grid.x / 2));
+    // plain forward sweeps in tile pairs (an even number of full tiles): every
+    // complex128 class; complex64 only in class 3, whose runs are 64 bytes (at
+    // n = 26 its classes 6 and 7 were 2 % slower in pairs, complex128's class 5
+    // 1.5 % faster)
+    if constexpr (SP >= 0 && (sizeof(R) == 8 || SP == 3)) {
+        constexpr int kPlainMask = kInit | kPhaseIn | kEOut | kNoStore;
+        if (mode == kFwd && !(a.flags & kPlainMask) && a.geo.tbits == (uint32_t)Tr<R>::TB && grid.x % 2 == 0 &&
+            grid.x >= 2) {
+            hipLaunchKernelGGL((k_fwd_pair<R, TM, SP>), dim3(grid.x / 2), block, 0, s, pair_args(a, grid.x / 2));
             return;
         }
     }
