@@ -49,6 +49,7 @@ struct qaoa_handle_s {
     void *psi = nullptr;   // state, 2^n amplitudes
     void *lam = nullptr;   // adjoint vector, allocated on first gradient
     void *cost = nullptr;  // cost diagonal, fp64 (c128) or fp32 (c64)
+    double cost_bound = 0; // |offset| + sum of |weights|: bounds |C(z)|
     double *parts = nullptr;
     size_t parts_cap = 0;  // doubles
     double *res = nullptr;
@@ -300,8 +301,13 @@ qaoa_status take_event(qaoa_handle h, hipEvent_t *ev)
     return QAOA_OK;
 }
 
-qaoa_status run_pass(qaoa_handle h, int mode, const qk::PassArgs &a)
+qaoa_status run_pass(qaoa_handle h, int mode, const qk::PassArgs &args)
 {
+    // passes whose phase arguments |gamma C| could leave the fast reduction's
+    // range are marked (the unused gamma fields are 0)
+    qk::PassArgs a = args;
+    if (std::max(std::fabs(a.gamma_in), std::fabs(a.gamma_out)) * h->cost_bound >= qk::near_phase_limit(c64(h)))
+        a.flags |= qk::kFarPhase;
     if (!h->profiling) {
         HIPCHECK(h, qk::launch_pass(mode, c64(h), a, nblocks(h), h->stream));
         return QAOA_OK;
@@ -599,6 +605,8 @@ qaoa_status create_common(int32_t n, int32_t precision, void *stream, qaoa_handl
 // diagonal, frees the upload once the stream has drained.
 qaoa_status build_cost(qaoa_handle h, const std::vector<qk::CostPiece> &pieces, double offset)
 {
+    h->cost_bound = std::fabs(offset);
+    for (const qk::CostPiece &pc : pieces) h->cost_bound += std::fabs(pc.w);
     const size_t bytes = pieces.size() * sizeof(qk::CostPiece);
     void *dev = nullptr;
     if (bytes) {

@@ -422,8 +422,10 @@ int static_spectators(const Geometry &g, bool c64, int mode)
 hipError_t launch_pass(int mode, bool c64, const PassArgs &a, uint64_t nblocks, hipStream_t s)
 {
     int sp = static_spectators(a.geo, c64, mode);
-    // a class's kernels fix whether their accesses stream
+    // a class's kernels fix whether their accesses stream, and take every phase
+    // argument in the fast reduction's range
     if (sp >= 0 && stream_class(sp) != ((a.flags & kStream) != 0)) sp = -1;
+    if (a.flags & kFarPhase) sp = -1;
     if (!c64) {
         switch (sp) {
         case 0: return launch_pass_sp<double, 0>(mode, a, nblocks, s);

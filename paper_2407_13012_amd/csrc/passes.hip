@@ -151,9 +151,9 @@ __global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>
 #pragma unroll
             for (int r = h; r < h + 4; ++r) {
                 R c, s;
-                phase_cs(-a.gamma_in, cu[r], c, s, PK);
+                phase_cs<true>(-a.gamma_in, cu[r], c, s, PK);
                 u[r] = cmul(a0, c, s);
-                phase_cs(-a.gamma_in, cw[r], c, s, PK);
+                phase_cs<true>(-a.gamma_in, cw[r], c, s, PK);
                 w[r] = cmul(a0, c, s);
             }
             __builtin_amdgcn_sched_barrier(0);

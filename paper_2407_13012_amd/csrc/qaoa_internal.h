@@ -43,8 +43,14 @@ enum PassFlags : int {
     kBetaAcc = 32,   // add the <lam|X|phi> partial to the existing one instead of overwriting
     kStream = 64,    // nontemporal loads/stores (tiles with long contiguous runs)
     kBetaAcc2 = 128, // kBetaAcc for the second rotation's partials (kBwdFuse)
-    kLamFromC = 256  // (kBwd) lam = C phi formed from the loaded phi instead of loaded
+    kLamFromC = 256, // (kBwd) lam = C phi formed from the loaded phi instead of loaded
+    kFarPhase = 512  // |gamma| max|C| may leave the fast phase reduction's range
 };
+
+// Below this bound on |gamma| max|C| every phase takes the fast reduction
+// (complex128: Cody-Waite for |x| < 1e6; complex64: the fp32 path for
+// |g1 C| < 4096), with a factor of 2 to spare for rounding of gamma and C.
+constexpr double near_phase_limit(bool c64) { return c64 ? 2048.0 : 5.0e5; }
 
 // One pass of a mixer layer.  A tile is the set of 2^TB basis indices that
 // agree outside `tile_bits` (TB = tile_bits(c64)); the pass rotates the qubits

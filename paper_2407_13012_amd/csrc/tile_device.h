@@ -282,9 +282,14 @@ __device__ __attribute__((noinline)) double2 sincos_far(double x)
     sincos(x, &s, &c);
     return make_double2(s, c);
 }
+// NEAR: the caller guarantees |x| < 1e6 (kernels of a spectator class; the
+// launcher sends passes whose |gamma| max|C| could reach it elsewhere), so the
+// out-of-line fallback and its call sites, which constrain register
+// allocation, are left out.
+template <bool NEAR = false>
 __device__ __forceinline__ void sincos_cw(double x, double &s, double &c, const PhaseK &K)
 {
-    if (!(fabs(x) < 1.0e6)) {
+    if (!NEAR && !(fabs(x) < 1.0e6)) {
         const double2 sc = sincos_far(x);
         s = sc.x;
         c = sc.y;
@@ -325,16 +330,19 @@ __device__ __forceinline__ void sincos_cw(double x, double &s, double &c, const 
 // clamped to [-pi/4, pi/4] so that even arguments too large for it (|x| beyond
 // ~2^50, far past fp32 phase resolution) give a unit-modulus factor.  K holds
 // the constants of the complex128 form and the split angle of the complex64 one.
+template <bool NEAR = false>
 __device__ __forceinline__ void phase_cs(double g, double cval, double &c, double &s, const PhaseK &K)
 {
-    sincos_cw(g * cval, s, c, K);
+    sincos_cw<NEAR>(g * cval, s, c, K);
 }
+// NEAR: the caller guarantees |g1 C| < 4096 (see sincos_cw), the fp32 path.
+template <bool NEAR = false>
 __device__ __forceinline__ void phase_cs(double g, float cval, float &c, float &s, const PhaseK32 &K)
 {
     float r;
     int q;
     const float p = K.g1 * cval;
-    if (fabsf(p) < 4096.0f) {
+    if (NEAR || fabsf(p) < 4096.0f) {
         const float pe = fmaf(K.g1, cval, -p);
         const float k = rintf(p * 0x1.45f306p-1f);          // 2/pi
         float rr = fmaf(-k, 0x1.922p+0f, p);                // pi/2: 12-bit head
@@ -779,7 +787,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
             for (int r = 0; r < NR; ++r)
                 if (VA(r)) {
                     R c, s;
-                    phase_cs(-a.gamma_in, cin[r], c, s, PK);
+                    phase_cs<(SP >= 0)>(-a.gamma_in, cin[r], c, s, PK);
                     v[r] = cmul(v[r], c, s);
                 }
         }
@@ -889,7 +897,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                     if (VC(r)) {
                         accG += (double)cv[r] * imcx(l[r], vscale(v[r], sb));
                         R c, s;
-                        phase_cs(a.gamma_out, cv[r], c, s, PK);
+                        phase_cs<(SP >= 0)>(a.gamma_out, cv[r], c, s, PK);
                         l[r] = cmul(l[r], c, s);
                     }
                 }
@@ -966,7 +974,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, uint64_t t, typenam
                         accG += (double)cv[r] * imcx(l[r], f[r]);
                         if (undo) {
                             R c, s;
-                            phase_cs(a.gamma_out, cv[r], c, s, PK);
+                            phase_cs<(SP >= 0)>(a.gamma_out, cv[r], c, s, PK);
                             f[r] = cmul(f[r], c, s);
                             l[r] = cmul(l[r], c, s);
                         }
@@ -1075,7 +1083,7 @@ __device__ __forceinline__ void tile_pass_fwd_fuse(const PassArgs &a, uint64_t t
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         R c, s;
-        phase_cs(-a.gamma_in, cv[r], c, s, PK);
+        phase_cs<(SP >= 0)>(-a.gamma_in, cv[r], c, s, PK);
         v[r] = cmul(vscale(v[r], s1), c, s);
     }
     mix_stage<2, TM2, true>(v, m2, tg);

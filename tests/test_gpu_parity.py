@@ -427,3 +427,35 @@ def test_workload_regular26_full_parity():
     gscale = max(np.max(np.abs(np.concatenate([dg_ref, db_ref]))), 1.0)
     assert abs(E32 - E_ref) / max(abs(E_ref), 1) <= 1e-4
     assert np.max(np.abs(np.concatenate([dg32 - dg_ref, db32 - db_ref]))) / gscale <= 1e-4
+
+
+# Phase arguments |gamma C| far beyond the fast reduction's range (weights of a
+# few 1e6): such passes leave the spectator-class kernels, whose phases assume
+# |gamma C| < 1e6 (complex128) or |g1 C| < 4096 (complex64), for the kernels
+# with the full-range fallback.  complex64 is compared with the oracle run on
+# the fp32-rounded cost diagonal (the rounding of C alone moves phases of 1e7
+# radians by about 1 radian).
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_phase_arguments_beyond_fast_range(prec):
+    n, p = 14, 2
+    inst = qi.erdos_renyi(n, 0.5, seed=[5, 14], weights="uniform", wlow=1.0e6, whigh=3.0e6)
+    C = oracle.cost_of(inst)
+    if prec == "c64":
+        C = C.astype(np.float32).astype(np.float64)
+    gamma = np.array([0.31, -0.47])
+    beta = np.array([0.6, 0.25])
+    assert np.abs(gamma).max() * np.abs(C).max() > 1e7
+    psi_ref = oracle.state(n, C, gamma, beta)
+    E_ref, dg_ref, db_ref = oracle.gradient(n, C, gamma, beta)
+    with H(inst, prec) as q:
+        psi = q.statevector(gamma, beta)
+        E, dg, db = q.gradient(gamma, beta)
+    gscale = np.abs(np.concatenate([dg_ref, db_ref])).max()
+    if prec == "c128":
+        assert np.max(np.abs(psi - psi_ref)) < 1e-12
+        assert abs(E - E_ref) <= 1e-10 * np.abs(C).max()
+        assert np.abs(np.concatenate([dg - dg_ref, db - db_ref])).max() <= 1e-9 * gscale
+    else:
+        assert np.max(np.abs(psi - psi_ref)) < 1e-5
+        assert abs(E - E_ref) <= 1e-4 * np.abs(C).max()
+        assert np.abs(np.concatenate([dg - dg_ref, db - db_ref])).max() <= 1e-4 * gscale
