@@ -183,6 +183,103 @@ __global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>
     }
 }
 
+// Layer-boundary forward sweep (tile_pass_fwd_fuse) in tile pairs: the two
+// tiles' rotations of layer l, the phase of layer l + 1 and its rotations,
+// interleaved; the arithmetic per amplitude is tile_pass_fwd_fuse's.
+template <typename R, bool TM, bool TM2, int SP>
+__global__ __launch_bounds__(Tr<R>::NT) __attribute__((amdgpu_waves_per_eu(Tr<R>::MINW))) void k_fuse_pair(PassArgs a)
+{
+    using V = typename Tr<R>::V;
+    using CT = typename Tr<R>::CT;
+    constexpr int WB = Tr<R>::WB, NR = Tr<R>::NR;
+    constexpr bool strm = stream_class(SP);
+    __shared__ V lds[kLdsTotal<R>];
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const Geometry &g = a.geo;
+    const Targets<SP> tg{g.tmask};
+    const uint64_t t0 = 2 * xcd_tile(blockIdx.x, a.xcd_g);
+    const uint64_t b0 = tile_base(t0, g), b1 = tile_base(t0 + 1, g);
+    V *psi = (V *)a.psi;
+    const CT *cost = (const CT *)a.cost;
+    CT cu[NR], cw[NR];
+    V u[NR], w[NR];
+    {
+        const uint64_t pC = dep(elem<2, WB>(lane, wave, 0), g);
+        const RegOffsets<2, WB> off(g);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            cu[r] = ld(&cost[b0 | pC | off(r)], strm);
+            cw[r] = ld(&cost[b1 | pC | off(r)], strm);
+        }
+    }
+    {
+        const uint64_t pA = dep(elem<0, WB>(lane, wave, 0), g);
+        const RegOffsets<0, WB> off(g);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            u[r] = ld(&psi[b0 | pA | off(r)], strm);
+            w[r] = ld(&psi[b1 | pA | off(r)], strm);
+        }
+    }
+    __builtin_amdgcn_s_setprio(0);
+    const R m1 = (R)a.mul_f, m2 = (R)a.mul_f2;
+    constexpr bool kSkipB = SP >= 4 && WB == 2;
+    mix_stage<0, TM, true>(u, m1, tg);
+    mix_stage<0, TM, true>(w, m1, tg);
+    if constexpr (kSkipB) {
+        xpose<0, 2>(u, lds, lane, wave);
+        xpose<0, 2>(w, lds, lane, wave);
+    } else {
+        xpose<0, 1>(u, lds, lane, wave);
+        xpose<0, 1>(w, lds, lane, wave);
+        mix_stage<1, TM, true>(u, m1, tg);
+        mix_stage<1, TM, true>(w, m1, tg);
+        xpose<1, 2>(u, lds, lane, wave);
+        xpose<1, 2>(w, lds, lane, wave);
+    }
+    mix_stage<2, TM, true>(u, m1, tg);
+    mix_stage<2, TM, true>(w, m1, tg);
+    {
+        const R s1 = (R)a.scl_f;
+        const auto PK = phase_consts<R>(-a.gamma_in);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            R c, s;
+            phase_cs<true>(-a.gamma_in, cu[r], c, s, PK);
+            u[r] = cmul(vscale(u[r], s1), c, s);
+            phase_cs<true>(-a.gamma_in, cw[r], c, s, PK);
+            w[r] = cmul(vscale(w[r], s1), c, s);
+        }
+    }
+    mix_stage<2, TM2, true>(u, m2, tg);
+    mix_stage<2, TM2, true>(w, m2, tg);
+    if constexpr (kSkipB) {
+        xpose<2, 0>(u, lds, lane, wave);
+        xpose<2, 0>(w, lds, lane, wave);
+    } else {
+        xpose<2, 1>(u, lds, lane, wave);
+        xpose<2, 1>(w, lds, lane, wave);
+        mix_stage<1, TM2, true>(u, m2, tg);
+        mix_stage<1, TM2, true>(w, m2, tg);
+        xpose<1, 0>(u, lds, lane, wave);
+        xpose<1, 0>(w, lds, lane, wave);
+    }
+    mix_stage<0, TM2, true>(u, m2, tg);
+    mix_stage<0, TM2, true>(w, m2, tg);
+    const R s2 = (R)a.scl_f2;
+    uint32_t tid2 = threadIdx.x;
+    asm volatile("" : "+v"(tid2));
+    const uint64_t pA = dep(elem<0, WB>(tid2 & 63u, tid2 >> 6, 0), g);
+    const RegOffsets<0, WB> off(g);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        st(vscale(u[r], s2), &psi[b0 | pA | off(r)], strm);
+        st(vscale(w[r], s2), &psi[b1 | pA | off(r)], strm);
+    }
+}
+
 // Layer-boundary passes (kFwdFuse, kBwdFuse); TM / TM2 are the factored forms
 // of the two rotations.  Same tile order and partial layout as k_pass.
 template <typename R, int MODE, bool TM, bool TM2, int SP>
@@ -247,6 +344,18 @@ void launch_fuse(const PassArgs &a, dim3 grid, hipStream_t s)
 {
     const dim3 block(Tr<R>::NT);
     const int sel = (a.tan_mode ? 2 : 0) + (a.tan_mode2 ? 1 : 0);
+    if constexpr (MODE == kFwdFuse && SP >= 0) {
+        // in tile pairs (an even number of full tiles)
+        if (a.geo.tbits == (uint32_t)Tr<R>::TB && grid.x % 2 == 0 && grid.x >= 2) {
+            const PassArgs b = pair_args(a, grid.x / 2);
+            const dim3 pg(grid.x / 2);
+            if (sel == 3) hipLaunchKernelGGL((k_fuse_pair<R, true, true, SP>), pg, block, 0, s, b);
+            else if (sel == 2) hipLaunchKernelGGL((k_fuse_pair<R, true, false, SP>), pg, block, 0, s, b);
+            else if (sel == 1) hipLaunchKernelGGL((k_fuse_pair<R, false, true, SP>), pg, block, 0, s, b);
+            else hipLaunchKernelGGL((k_fuse_pair<R, false, false, SP>), pg, block, 0, s, b);
+            return;
+        }
+    }
     if (sel == 3) hipLaunchKernelGGL((k_pass_fuse<R, MODE, true, true, SP>), grid, block, 0, s, a);
     else if (sel == 2) hipLaunchKernelGGL((k_pass_fuse<R, MODE, true, false, SP>), grid, block, 0, s, a);
     else if (sel == 1) hipLaunchKernelGGL((k_pass_fuse<R, MODE, false, true, SP>), grid, block, 0, s, a);
