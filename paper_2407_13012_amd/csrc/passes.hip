@@ -1,4 +1,5 @@
-// Pass kernels (k_pass, k_pass_fuse) of one precision and one spectator class.
+// Pass kernels (k_pass, k_pass_fuse, and the tile-pair kernels k_fwd_pair,
+// k_init_pair, k_fuse_pair) of one precision and one spectator class.
 //
 // This file is compiled once per (QK_PASS_REAL, QK_PASS_SP): QK_PASS_REAL is
 // double (complex128 tiles) or float (complex64 tiles), QK_PASS_SP the number
@@ -7,9 +8,12 @@
 // target mask at run time.  With S fixed every rotation stage of the tile code
 // is taken or left out at compile time: a stage under a run-time branch leaves
 // its results in new registers and the join after it copies them back, about
-// a quarter of the VALU work of a two-vector pass.  The tile code itself (load,
-// phase, rotations, transposes, reductions, stores) is in tile_device.h; the
-// kernels and the host launcher of each translation unit are its own.
+// a quarter of the VALU work of a two-vector pass.  Such kernels also take the
+// pass's access kind (streaming or not) and the phase range as constants; the
+// launcher sends passes that disagree to the run-time-mask kernels.  The tile
+// code itself (load, phase, rotations, transposes, reductions, stores) is in
+// tile_device.h; the kernels and the host launcher of each translation unit
+// are its own.
 #include "tile_device.h"
 
 #ifndef QK_PASS_REAL
